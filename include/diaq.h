@@ -1,0 +1,283 @@
+/*
+ * diaq.h — C ABI of libdiaq_hip, an MI355X (gfx950) implementation of the
+ * DiaQ state-vector hot path (Chundury, Li, Suh, Mueller: "DiaQ: Efficient
+ * State-Vector Quantum Simulation", arXiv:2405.01250).
+ *
+ * What the library computes
+ * -------------------------
+ * A quantum gate acting on k <= 3 target qubits (plus up to 3 control
+ * qubits) of an n-qubit register is expanded to the 2^n x 2^n time-step
+ * unitary I_above (x) Gate (x) I_below (Sec. II-C) and stored in the DiaQ
+ * format (Sec. IV): a set of diagonals, each identified by its index
+ * dIndex = column - row, each stored compactly with exactly N - |dIndex|
+ * entries (N = 2^n).  The state vector is advanced by the DiaQ sparse
+ * matrix-vector product (Alg. 2).  Around that sit the DiaQ matrix product
+ * used for gate fusion (Alg. 1, Sec. VI), the transpose-by-relabelling of
+ * Sec. IV, expectation values, adjoint (reverse-sweep) gradients and
+ * batched circuits.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Qubit order is little-endian: qubit q is bit q of an amplitude index,
+ *    so a one-qubit gate on q has diagonals at 0 and +-2^q.  (The paper's
+ *    "first qubit", H (x) I_8 in its Fig. 2, is qubit n-1 here.)
+ *  - Complex numbers are interleaved (re, im).  DIAQ_C128 = two doubles,
+ *    DIAQ_C64 = two floats (the float/double option of Sec. V).
+ *  - State vectors, scratch vectors and DiaQ values live in device memory
+ *    owned by the caller unless stated otherwise; pointers must be 16-byte
+ *    aligned (256-byte alignment is recommended, the byte-alignment option
+ *    of Sec. V).
+ *  - Every call is asynchronous on the context's HIP stream, except the
+ *    calls documented as returning host results, which synchronise it.
+ *  - Every call returns a diaq_status_t; no C++ exception crosses the ABI.
+ *    On error the outputs are left untouched and diaq_last_error() returns
+ *    a thread-local message.
+ *  - A context is not thread-safe; use one context per host thread/stream.
+ */
+#ifndef DIAQ_H
+#define DIAQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Status codes, dtypes, handles                                       */
+/* ------------------------------------------------------------------ */
+
+typedef enum diaq_status {
+  DIAQ_OK = 0,
+  DIAQ_ERR_INVALID_ARGUMENT = 1, /* bad qubit index, NULL pointer, aliasing */
+  DIAQ_ERR_NOT_MULTIPLYABLE = 2, /* dimension mismatch (Alg. 1 / Alg. 2 guard) */
+  DIAQ_ERR_OUT_OF_MEMORY = 3,    /* device or host allocation failed */
+  DIAQ_ERR_DEVICE = 4,           /* a HIP runtime call failed */
+  DIAQ_ERR_UNSUPPORTED = 5       /* valid request that this build does not do */
+} diaq_status_t;
+
+typedef enum diaq_dtype {
+  DIAQ_C64 = 0,  /* complex float, 8 bytes per element */
+  DIAQ_C128 = 1  /* complex double, 16 bytes per element */
+} diaq_dtype_t;
+
+typedef struct diaq_ctx* diaq_ctx_t; /* device, stream, workspace, tuning */
+typedef struct diaq_dia* diaq_dia_t; /* one DiaQ matrix (Sec. IV) */
+
+/* ------------------------------------------------------------------ */
+/* Gates                                                               */
+/* ------------------------------------------------------------------ */
+
+/* Gate kinds.  c = cos(t/2), s = sin(t/2) for an angle t = params[0].
+ * Multi-target matrices index their rows/columns with targets[0] as the
+ * least-significant local bit.  Controlled kinds put the control qubits in
+ * controls[] and the target(s) in targets[]. */
+typedef enum diaq_gate_kind {
+  DIAQ_GATE_I = 0,
+  DIAQ_GATE_H = 1,      /* (1/sqrt2)[[1,1],[1,-1]] */
+  DIAQ_GATE_X = 2,
+  DIAQ_GATE_Y = 3,
+  DIAQ_GATE_Z = 4,
+  DIAQ_GATE_S = 5,      /* diag(1, i) */
+  DIAQ_GATE_SDG = 6,    /* diag(1, -i) */
+  DIAQ_GATE_T = 7,      /* diag(1, e^{i pi/4}) */
+  DIAQ_GATE_TDG = 8,    /* diag(1, e^{-i pi/4}) */
+  DIAQ_GATE_SX = 9,     /* (1/2)[[1+i, 1-i],[1-i, 1+i]] */
+  DIAQ_GATE_RX = 10,    /* [[c, -is],[-is, c]]                 = exp(-i t X/2) */
+  DIAQ_GATE_RY = 11,    /* [[c, -s],[s, c]]                     = exp(-i t Y/2) */
+  DIAQ_GATE_RZ = 12,    /* diag(e^{-it/2}, e^{it/2})            = exp(-i t Z/2) */
+  DIAQ_GATE_P = 13,     /* diag(1, e^{it}) */
+  DIAQ_GATE_U3 = 14,    /* params (theta, phi, lambda):
+                           [[c, -e^{i lambda} s],[e^{i phi} s, e^{i(phi+lambda)} c]] */
+  DIAQ_GATE_SWAP = 15,  /* 2 targets: exchanges local states 01 and 10 */
+  DIAQ_GATE_RXX = 16,   /* 2 targets: exp(-i t X(x)X/2) */
+  DIAQ_GATE_RYY = 17,   /* 2 targets: exp(-i t Y(x)Y/2) */
+  DIAQ_GATE_RZZ = 18,   /* 2 targets: diag(e^{-it/2}, e^{it/2}, e^{it/2}, e^{-it/2}) */
+  DIAQ_GATE_MATRIX = 19 /* k targets: the 2^k x 2^k complex128 row-major
+                           matrix at diaq_gate_t.matrix (host memory) */
+} diaq_gate_kind_t;
+
+#define DIAQ_MAX_TARGETS 3
+#define DIAQ_MAX_CONTROLS 3
+
+/* One gate.  Controlled gates (CX = X with one control, CZ, CP, CCX, CSWAP,
+ * controlled rotations) are the base kind plus controls: where every
+ * control bit of an amplitude index is 1 the local matrix acts on the
+ * targets, elsewhere the identity does.
+ *
+ * Differentiation: a gate whose kind is a rotation (RX, RY, RZ, P, RXX,
+ * RYY, RZZ, controlled or not) may name a gradient slot.  With
+ * U = exp(-i a G / 2), a = params[0], the adjoint sweep adds
+ * param_scale * dE/da to grad[param_index]; param_scale is the caller's
+ * chain factor d a / d theta (for example 2 when a = 2 * gamma). */
+typedef struct diaq_gate {
+  int32_t kind;                        /* diaq_gate_kind_t */
+  int32_t ntargets;                    /* 1..3, must match the kind */
+  int32_t ncontrols;                   /* 0..3 */
+  int32_t targets[DIAQ_MAX_TARGETS];   /* distinct qubits in [0, n) */
+  int32_t controls[DIAQ_MAX_CONTROLS]; /* distinct, disjoint from targets */
+  double params[3];                    /* angles in radians, per kind */
+  int32_t param_index;                 /* -1: constant gate */
+  double param_scale;                  /* chain factor, see above */
+  const double* matrix;                /* DIAQ_GATE_MATRIX only, else NULL */
+} diaq_gate_t;
+
+/* ------------------------------------------------------------------ */
+/* Context                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Thread-local text of the last error raised on this host thread. */
+const char* diaq_last_error(void);
+const char* diaq_status_string(diaq_status_t status);
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The context owns a growing
+ * device workspace for expanded diagonals and reduction partials. */
+diaq_status_t diaq_create(int32_t device, void* hip_stream, diaq_ctx_t* out);
+diaq_status_t diaq_set_stream(diaq_ctx_t ctx, void* hip_stream);
+diaq_status_t diaq_synchronize(diaq_ctx_t ctx);
+/* Frees the workspace; DiaQ matrices created on the context stay valid. */
+diaq_status_t diaq_destroy(diaq_ctx_t ctx);
+
+/* ------------------------------------------------------------------ */
+/* DiaQ matrices (Sec. IV)                                              */
+/* ------------------------------------------------------------------ */
+
+/* Wrap or allocate a DiaQ matrix of dimension 2^nqubits with `ndiag`
+ * diagonals at `offsets` (host, col - row, strictly ascending, each
+ * |offset| < 2^nqubits).  The values of diagonal k are packed after those
+ * of diagonals 0..k-1 and hold N - |offsets[k]| elements, element t being
+ * A[t + max(0,-d), t + max(0,d)] (the compact layout of Sec. IV).
+ * `values` is a caller-owned device buffer of that total size, or NULL to
+ * let the library allocate one (zero-filled, freed by diaq_dia_free). */
+diaq_status_t diaq_dia_create(diaq_ctx_t ctx, int32_t nqubits,
+                              diaq_dtype_t dtype, int32_t ndiag,
+                              const int64_t* offsets, void* values,
+                              diaq_dia_t* out);
+/* Shape query.  Any output pointer may be NULL. */
+diaq_status_t diaq_dia_info(diaq_dia_t A, int32_t* nqubits, int32_t* ndiag,
+                            int32_t* dtype, int64_t* nvalues, void** values);
+/* Copy the offsets (ndiag entries) and packing starts (ndiag + 1 entries)
+ * to host arrays; either may be NULL. */
+diaq_status_t diaq_dia_offsets(diaq_dia_t A, int64_t* offsets,
+                               int64_t* starts);
+/* Transpose by relabelling (Sec. IV: the diagonal indices change sign and
+ * the compact diagonals are reused unchanged).  `out` is a new handle that
+ * shares A's values (A must outlive it); conjugate != 0 gives A^dagger. */
+diaq_status_t diaq_dia_transpose(diaq_dia_t A, int32_t conjugate,
+                                 diaq_dia_t* out);
+/* Release a handle (and the values, if the library allocated them). */
+diaq_status_t diaq_dia_free(diaq_dia_t A);
+
+/* ------------------------------------------------------------------ */
+/* Gate expansion: the time-step unitary of Sec. II-C in DiaQ form      */
+/* ------------------------------------------------------------------ */
+
+/* Host-only query: the diagonal indices the expanded gate occupies (sorted
+ * ascending) and the number of stored elements.  The indices are the
+ * differences scatter(c) - scatter(r) over the structurally non-zero
+ * entries M[r][c] of the gate's local matrix, plus 0 for controlled gates;
+ * scatter places local bit j at qubit targets[j] (Sec. II-C; for
+ * I_a (x) M (x) I_b this is Alg. 3's dim_b * dIndex).  `offsets` may be
+ * NULL; at most 27 entries are written. */
+diaq_status_t diaq_from_gate_query(const diaq_gate_t* gate, int32_t nqubits,
+                                   int32_t* ndiag, int64_t* offsets,
+                                   int64_t* nvalues);
+/* Expand `gate` on an n-qubit register into a new DiaQ matrix whose values
+ * the library allocates (freed by diaq_dia_free).  Element (i, j) of the
+ * expansion is M[loc(i)][loc(j)] when i and j agree outside the targets
+ * and all controls of i are 1, the identity's delta(i,j) when a control is
+ * 0, and 0 otherwise; loc gathers the target bits. */
+diaq_status_t diaq_from_gate(diaq_ctx_t ctx, const diaq_gate_t* gate,
+                             int32_t nqubits, diaq_dtype_t dtype,
+                             diaq_dia_t* out);
+
+/* Pauli-sum observable H = sum_t coef_t * P_t as a DiaQ matrix.  Term t is
+ * X^x Z^z up to the phase i^{popcount(x & z)} (so x = z = bit q is Y_q):
+ * xmask[t], zmask[t] are bit masks over qubits, coef[t] a real weight.  Each
+ * term occupies the diagonals (i xor x) - i; equal indices are summed. */
+diaq_status_t diaq_from_pauli_sum(diaq_ctx_t ctx, int32_t nqubits,
+                                  diaq_dtype_t dtype, int32_t nterms,
+                                  const uint64_t* xmask, const uint64_t* zmask,
+                                  const double* coef, diaq_dia_t* out);
+
+/* ------------------------------------------------------------------ */
+/* Kernels                                                              */
+/* ------------------------------------------------------------------ */
+
+#define DIAQ_TRANSPOSE 1u /* apply A^T  (indices negated, Sec. IV) */
+#define DIAQ_CONJUGATE 2u /* conjugate the stored values */
+#define DIAQ_ADJOINT 3u   /* apply A^dagger */
+
+/* DiaQ sparse matrix-vector product (Alg. 2): y <- op(A) x, where op is
+ * selected by `flags`.  y is overwritten, not accumulated; x and y are
+ * device vectors of 2^n elements of A's dtype and must not overlap
+ * (DIAQ_ERR_INVALID_ARGUMENT), except that a matrix whose only diagonal is
+ * the principal one may run in place (x == y). */
+diaq_status_t diaq_spmv(diaq_ctx_t ctx, diaq_dia_t A, const void* x, void* y,
+                        uint32_t flags);
+
+/* DiaQ matrix product (Alg. 1): out <- second * first, i.e. the matrix that
+ * applies `first` and then `second`.  Every pair of diagonals (a of first,
+ * b of second) contributes to diagonal a + b; contributions to one index
+ * are summed in ascending order of a.  Result diagonals whose elements all
+ * have |value| <= drop_tol are dropped (drop_tol = 0 drops exact zeros
+ * only).  Dimension or dtype mismatch: DIAQ_ERR_NOT_MULTIPLYABLE.  The
+ * library allocates the result's values.  Synchronises the stream. */
+diaq_status_t diaq_fuse(diaq_ctx_t ctx, diaq_dia_t first, diaq_dia_t second,
+                        double drop_tol, diaq_dia_t* out);
+
+/* ------------------------------------------------------------------ */
+/* Circuits                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Execution plan for diaq_apply_circuit.  A zero-filled plan (or NULL) is
+ * the plain path: one expansion and one Alg. 2 product per gate. */
+typedef struct diaq_plan {
+  int32_t fuse;             /* 1: gate-level fusion (Alg. 1 on the local
+                               matrices, diagonal gates absorbed) */
+  int32_t max_fused_qubits; /* cap on a fused group's non-diagonal qubits
+                               (1..3, 0 = 2) */
+  int32_t kron;             /* 1: Alg. 3 products, no expanded diagonals */
+  int32_t rows_per_thread;  /* SpMV rows per lane (0 = tuned default) */
+  int32_t block;            /* SpMV workgroup size (0 = tuned default) */
+  int32_t reserved[3];
+} diaq_plan_t;
+
+/* state <- U_{end-1} ... U_{begin} state for gates[begin, end) with
+ * 0 <= begin <= end <= ngates (a saved state plus a gate index resumes a
+ * run).  `state` and `scratch` are distinct device vectors of 2^n
+ * elements; scratch contents are clobbered.  Diagonals are expanded into
+ * the context workspace. */
+diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates,
+                                 int64_t ngates, int64_t begin, int64_t end,
+                                 int32_t nqubits, diaq_dtype_t dtype,
+                                 void* state, void* scratch,
+                                 const diaq_plan_t* plan);
+
+/* Expectation value <psi|H|phi> (phi = NULL means phi = psi) written to
+ * out[0] (real part) and out[1] (imaginary part), host memory.  The sum is
+ * reduced in a fixed order, so repeated calls are bitwise equal.
+ * Synchronises the stream. */
+diaq_status_t diaq_expect(diaq_ctx_t ctx, diaq_dia_t H, const void* psi,
+                          const void* phi, double* out);
+
+/* Adjoint gradient of E(theta) = <psi|H|psi>, psi = U_G...U_1 psi0.
+ * Forward pass, lambda = H psi, then a reverse sweep that for g = G..1
+ * adds param_scale * Im<lambda|G_g|psi> to grad[param_index] of every
+ * differentiable gate and steps psi and lambda back through U_g^dagger (the
+ * conjugate-transposed DiaQ matrix of the same expansion).  `work` holds
+ * 3 * 2^n elements of device memory.  Writes *expval and grad[0..nparams)
+ * (host, zeroed first).  Synchronises the stream. */
+diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates,
+                                int64_t ngates, int32_t nqubits,
+                                diaq_dtype_t dtype, diaq_dia_t H,
+                                const void* psi0, void* work,
+                                int64_t nparams, double* expval,
+                                double* grad);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIAQ_H */
