@@ -166,6 +166,12 @@ diaq_status_t diaq_dia_offsets(diaq_dia_t A, int64_t* offsets,
  * shares A's values (A must outlive it); conjugate != 0 gives A^dagger. */
 diaq_status_t diaq_dia_transpose(diaq_dia_t A, int32_t conjugate,
                                  diaq_dia_t* out);
+/* Copy the stored values (diaq_dia_info's nvalues elements, packed in
+ * stored order) to `dst`: device memory if dst_on_host == 0, else host
+ * memory.  The numpy-to-DiaQ converters of Sec. V go the other way through
+ * diaq_dia_create with caller-filled values.  Synchronises the stream. */
+diaq_status_t diaq_dia_copy_values(diaq_ctx_t ctx, diaq_dia_t A, void* dst,
+                                   int32_t dst_on_host);
 /* Release a handle (and the values, if the library allocated them). */
 diaq_status_t diaq_dia_free(diaq_dia_t A);
 

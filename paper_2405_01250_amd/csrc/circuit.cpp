@@ -1,0 +1,194 @@
+// circuit.cpp -- circuit-level drivers: plain per-gate state evolution and
+// the adjoint (reverse-sweep) gradient.
+//
+// State evolution (Sec. II-A, Sec. VI): each gate's time-step unitary is
+// expanded into the context's diagonal workspace and applied by the DiaQ
+// SpMV, ping-ponging between the caller's state and scratch vectors.  All
+// work is queued on one stream; nothing returns to the host until the
+// caller reads the state.
+#include <algorithm>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace diaq {
+
+namespace {
+
+struct Prepared {
+  std::vector<LocalGate> lg;
+  std::vector<std::vector<int64_t>> offs;
+  int64_t max_values = 0;
+};
+
+diaq_status_t prepare_gates(const diaq_gate_t* gates, int64_t ngates, int n, Prepared* p) {
+  p->lg.resize(size_t(ngates));
+  p->offs.resize(size_t(ngates));
+  for (int64_t g = 0; g < ngates; g++) {
+    diaq_status_t st = local_gate(&gates[g], n, &p->lg[g]);
+    if (st != DIAQ_OK) return fail(st, "gate %lld: %s", (long long)g, diaq_last_error());
+    p->offs[g] = gate_offsets(p->lg[g]);
+    p->max_values = std::max<int64_t>(p->max_values, packing_starts(p->offs[g], n).back());
+  }
+  return DIAQ_OK;
+}
+
+// Expand gate g into the workspace and apply it (or its adjoint) from *x
+// into *y; swaps the pointers unless the gate ran in place.
+diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t>& offs, int n, diaq_dtype_t dt,
+                   bool adjoint, void** x, void** y) {
+  const std::vector<int64_t> st = packing_starts(offs, n);
+  DIAQ_TRY(launch_expand(ctx, lg, n, dt, offs, st, ctx->diag.ptr));
+  SpmvOp op;
+  op.n = n;
+  op.dtype = dt;
+  op.nd = int(offs.size());
+  op.host_off = offs.data();
+  op.host_start = st.data();
+  op.values = ctx->diag.ptr;
+  op.transpose = adjoint;
+  op.conjugate = adjoint;
+  op.qubit_mask = lg.tmask;
+  if (offs.size() == 1 && offs[0] == 0) return launch_spmv(ctx, op, *x, *x);
+  DIAQ_TRY(launch_spmv(ctx, op, *x, *y));
+  std::swap(*x, *y);
+  return DIAQ_OK;
+}
+
+diaq_status_t check_vectors(int n, diaq_dtype_t dt, const void* a, const void* b) {
+  if (dt != DIAQ_C64 && dt != DIAQ_C128) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad dtype");
+  if (n < 1 || n > 34) return fail(DIAQ_ERR_INVALID_ARGUMENT, "nqubits %d out of range", n);
+  if (!a || !b) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL vector");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "vector not 16-byte aligned");
+  const size_t bytes = (size_t(1) << n) * elem_bytes(dt);
+  const char* ab = static_cast<const char*>(a);
+  const char* bb = static_cast<const char*>(b);
+  if (ab < bb + bytes && bb < ab + bytes) return fail(DIAQ_ERR_INVALID_ARGUMENT, "state and scratch overlap");
+  return DIAQ_OK;
+}
+
+}  // namespace
+
+// Forward pass over gates[begin, end); *result receives the buffer that holds
+// the final state (state or scratch).
+diaq_status_t run_plain(diaq_ctx* ctx, const Prepared& p, int64_t begin, int64_t end, int n, diaq_dtype_t dt,
+                        void* state, void* scratch, void** result) {
+  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(p.max_values) * elem_bytes(dt)));
+  void* x = state;
+  void* y = scratch;
+  for (int64_t g = begin; g < end; g++) DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], n, dt, false, &x, &y));
+  *result = x;
+  return DIAQ_OK;
+}
+
+}  // namespace diaq
+
+using namespace diaq;
+
+extern "C" {
+
+diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t ngates, int64_t begin,
+                                 int64_t end, int32_t nqubits, diaq_dtype_t dtype, void* state, void* scratch,
+                                 const diaq_plan_t* plan) {
+  try {
+    if (!ctx) return fail(DIAQ_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (ngates < 0 || (ngates > 0 && !gates)) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad gate list");
+    if (begin < 0 || end < begin || end > ngates)
+      return fail(DIAQ_ERR_INVALID_ARGUMENT, "gate range [%lld, %lld) outside [0, %lld]", (long long)begin,
+                  (long long)end, (long long)ngates);
+    DIAQ_TRY(check_vectors(nqubits, dtype, state, scratch));
+    if (plan && (plan->fuse || plan->kron)) return fail(DIAQ_ERR_UNSUPPORTED, "plan options not built yet");
+    Prepared p;
+    DIAQ_TRY(prepare_gates(gates + begin, end - begin, nqubits, &p));
+    const int saved_rows = ctx->spmv_rows;
+    if (plan && plan->rows_per_thread) ctx->spmv_rows = plan->rows_per_thread;
+    void* res = nullptr;
+    diaq_status_t st = run_plain(ctx, p, 0, end - begin, nqubits, dtype, state, scratch, &res);
+    ctx->spmv_rows = saved_rows;
+    DIAQ_TRY(st);
+    if (res != state)
+      DIAQ_HIP(hipMemcpyAsync(state, res, (size_t(1) << nqubits) * elem_bytes(dtype), hipMemcpyDeviceToDevice,
+                              ctx->stream));
+    return DIAQ_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t ngates, int32_t nqubits,
+                                diaq_dtype_t dtype, diaq_dia_t H, const void* psi0, void* work, int64_t nparams,
+                                double* expval, double* grad) {
+  try {
+    if (!ctx || !H || !psi0 || !work || !expval || (nparams > 0 && !grad))
+      return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (ngates < 0 || (ngates > 0 && !gates)) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad gate list");
+    if (H->nqubits != nqubits || H->dtype != dtype)
+      return fail(DIAQ_ERR_NOT_MULTIPLYABLE, "observable is 2^%d, register 2^%d", H->nqubits, nqubits);
+    const size_t N = size_t(1) << nqubits;
+    const size_t vb = N * elem_bytes(dtype);
+    char* w = static_cast<char*>(work);
+    void* psi = w;
+    void* lam = w + vb;
+    void* tmp = w + 2 * vb;
+    DIAQ_TRY(check_vectors(nqubits, dtype, psi, lam));
+    {
+      const char* p0 = static_cast<const char*>(psi0);
+      if (p0 < w + 3 * vb && w < p0 + vb) return fail(DIAQ_ERR_INVALID_ARGUMENT, "psi0 overlaps work");
+    }
+    Prepared p;
+    DIAQ_TRY(prepare_gates(gates, ngates, nqubits, &p));
+    std::vector<LocalGate> gens(static_cast<size_t>(ngates));
+    std::vector<int> diff(static_cast<size_t>(ngates), 0);
+    for (int64_t g = 0; g < ngates; g++) {
+      if (gates[g].param_index < 0) continue;
+      if (gates[g].param_index >= nparams)
+        return fail(DIAQ_ERR_INVALID_ARGUMENT, "gate %lld: param_index %d >= nparams %lld", (long long)g,
+                    gates[g].param_index, (long long)nparams);
+      gens[g] = p.lg[g];
+      if (!local_generator(&gates[g], &gens[g]))
+        return fail(DIAQ_ERR_UNSUPPORTED, "gate %lld: kind %d is not a rotation with a generator", (long long)g,
+                    gates[g].kind);
+      diff[g] = 1;
+    }
+    // device slots: [0] = <psi|H|psi>, [1 + g] = <lam|G_g|psi>
+    DIAQ_TRY(ensure(ctx, &ctx->aux, size_t(ngates + 1) * 2 * sizeof(double) + 256));
+    double* dots = static_cast<double*>(ctx->aux.ptr);
+    DIAQ_HIP(hipMemsetAsync(dots, 0, size_t(ngates + 1) * 2 * sizeof(double), ctx->stream));
+
+    // forward: psi = U psi0
+    DIAQ_HIP(hipMemcpyAsync(psi, psi0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    void* res = nullptr;
+    DIAQ_TRY(run_plain(ctx, p, 0, ngates, nqubits, dtype, psi, tmp, &res));
+    if (res != psi) std::swap(psi, tmp);
+    // lam = H psi ; E = <psi|lam>
+    DIAQ_TRY(launch_spmv(ctx, op_of(H, H->transposed, H->conjugated), psi, lam));
+    LocalGate ident;
+    std::memset(&ident, 0, sizeof(ident));
+    ident.k = 1;
+    ident.targets[0] = 0;
+    ident.m[0][0][0] = 1;
+    ident.m[1][1][0] = 1;
+    DIAQ_TRY(launch_generator_dot(ctx, ident, nqubits, dtype, psi, lam, dots));
+    // reverse sweep
+    for (int64_t g = ngates - 1; g >= 0; g--) {
+      if (diff[g]) DIAQ_TRY(launch_generator_dot(ctx, gens[g], nqubits, dtype, lam, psi, dots + 2 * (g + 1)));
+      if (g == 0) break;
+      DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], nqubits, dtype, true, &psi, &tmp));
+      DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], nqubits, dtype, true, &lam, &tmp));
+    }
+    const size_t rb = size_t(ngates + 1) * 2 * sizeof(double);
+    DIAQ_TRY(ensure_pinned(ctx, rb));
+    DIAQ_HIP(hipMemcpyAsync(ctx->pinned, dots, rb, hipMemcpyDeviceToHost, ctx->stream));
+    DIAQ_HIP(hipStreamSynchronize(ctx->stream));
+    *expval = ctx->pinned[0];
+    for (int64_t j = 0; j < nparams; j++) grad[j] = 0.0;
+    for (int64_t g = 0; g < ngates; g++)
+      if (diff[g]) grad[gates[g].param_index] += gates[g].param_scale * ctx->pinned[2 * (g + 1) + 1];
+    return DIAQ_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// internal.hpp -- shared declarations of libdiaq_hip (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "diaq.h"
+
+namespace diaq {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+diaq_status_t fail(diaq_status_t st, const char* fmt, ...);
+void clear_error();
+
+#define DIAQ_HIP(expr)                                                       \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return ::diaq::fail(e_ == hipErrorOutOfMemory ? DIAQ_ERR_OUT_OF_MEMORY \
+                                                    : DIAQ_ERR_DEVICE,       \
+                          "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+#define DIAQ_TRY(expr)                  \
+  do {                                  \
+    diaq_status_t s_ = (expr);          \
+    if (s_ != DIAQ_OK) return s_;       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Complex helpers (interleaved re/im, 8- or 16-byte elements)
+// ---------------------------------------------------------------------------
+
+template <typename R> struct Cx;
+template <> struct Cx<double> { using V = double2; };
+template <> struct Cx<float> { using V = float2; };
+
+inline size_t elem_bytes(diaq_dtype_t t) { return t == DIAQ_C128 ? 16 : 8; }
+
+// ---------------------------------------------------------------------------
+// Objects behind the opaque handles
+// ---------------------------------------------------------------------------
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace diaq
+
+struct diaq_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 256;
+  diaq::Workspace diag;     // expanded diagonals for circuit runs
+  diaq::Workspace red;      // reduction partials
+  diaq::Workspace aux;      // small per-call device tables
+  double* pinned = nullptr; // host-pinned landing zone for results
+  size_t pinned_bytes = 0;
+  // SpMV tuning (0 = defaults)
+  int spmv_block = 0;
+  int spmv_rows = 0;
+};
+
+struct diaq_dia {
+  int32_t nqubits = 0;
+  int32_t ndiag = 0;
+  diaq_dtype_t dtype = DIAQ_C128;
+  std::vector<int64_t> offsets;  // ascending, stored order
+  std::vector<int64_t> starts;   // ndiag + 1
+  void* values = nullptr;        // device
+  int64_t* dmeta = nullptr;      // device: offsets[ndiag] then starts[ndiag+1]
+  bool owns_values = false;
+  bool transposed = false;       // apply with negated offsets
+  bool conjugated = false;       // apply with conjugated values
+  uint64_t qubit_mask = 0;       // qubits whose bit the matrix may flip
+  int device = 0;
+};
+
+namespace diaq {
+
+// ---------------------------------------------------------------------------
+// Host-side gate algebra (gates.cpp)
+// ---------------------------------------------------------------------------
+
+struct LocalGate {
+  int k = 0;                         // number of targets
+  int nc = 0;                        // number of controls
+  int targets[3] = {0, 0, 0};
+  int controls[3] = {0, 0, 0};
+  double m[8][8][2];                 // local matrix, [row][col][re/im]
+  bool structural[8][8];             // entry may be non-zero for this kind
+  uint64_t tmask = 0, cmask = 0;
+};
+
+// Validate a gate against an n-qubit register and build its local matrix.
+diaq_status_t local_gate(const diaq_gate_t* g, int n, LocalGate* out);
+// Generator G of a rotation kind (U = exp(-i a G / 2)); false if none.
+bool local_generator(const diaq_gate_t* g, LocalGate* out);
+// Sorted diagonal indices of the expanded gate.
+std::vector<int64_t> gate_offsets(const LocalGate& lg);
+// Packing starts for offsets of an n-qubit matrix.
+std::vector<int64_t> packing_starts(const std::vector<int64_t>& offs, int n);
+bool is_diagonal_kind(const diaq_gate_t* g);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (one .hip file each)
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxArgDiags = 27;
+
+// Diagonal list passed by value to kernels.
+struct DiagArgs {
+  int32_t nd;
+  int32_t pad;
+  int64_t off[kMaxArgDiags];
+  int64_t start[kMaxArgDiags];
+};
+
+// expand.hip
+diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n,
+                            diaq_dtype_t dt, const std::vector<int64_t>& offs,
+                            const std::vector<int64_t>& starts, void* values);
+diaq_status_t launch_pauli_dia(diaq_ctx* ctx, int n, diaq_dtype_t dt,
+                               const std::vector<int64_t>& offs,
+                               const std::vector<int64_t>& starts,
+                               const uint64_t* xm, const uint64_t* zm,
+                               const double* coef, int nterms, void* values);
+
+// spmv.hip.  The matrix is (offsets, starts, values) with optional
+// transpose / conjugation; offsets come from `args` when nd <= kMaxArgDiags,
+// else from the device table dmeta.
+struct SpmvOp {
+  int n = 0;
+  diaq_dtype_t dtype = DIAQ_C128;
+  int nd = 0;
+  const int64_t* host_off = nullptr;    // host view (for planning)
+  const int64_t* host_start = nullptr;
+  const int64_t* dmeta = nullptr;       // device table (nd > kMaxArgDiags)
+  const void* values = nullptr;
+  bool transpose = false;
+  bool conjugate = false;
+  uint64_t qubit_mask = 0;
+};
+diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x,
+                          void* y);
+
+// expect.hip: out2 = <psi | op | phi> reduced deterministically; result left
+// in device memory at dres (2 doubles).
+diaq_status_t launch_expect(diaq_ctx* ctx, const SpmvOp& op, const void* psi,
+                            const void* phi, double* dres);
+// <lam | G | psi> for a local generator applied by index bit manipulation.
+diaq_status_t launch_generator_dot(diaq_ctx* ctx, const LocalGate& gen, int n,
+                                   diaq_dtype_t dt, const void* lam,
+                                   const void* psi, double* dres);
+
+// fuse.hip
+diaq_status_t fuse_dia(diaq_ctx* ctx, const diaq_dia* first,
+                       const diaq_dia* second, double drop_tol,
+                       diaq_dia** out);
+
+// Workspace growth (never shrinks).
+diaq_status_t ensure(diaq_ctx* ctx, Workspace* w, size_t bytes);
+diaq_status_t ensure_pinned(diaq_ctx* ctx, size_t bytes);
+
+// Qubit mask of the off-diagonal structure implied by an offset list.
+uint64_t mask_from_offsets(const std::vector<int64_t>& offs);
+
+diaq_status_t new_dia(diaq_ctx* ctx, int n, diaq_dtype_t dt,
+                      const std::vector<int64_t>& offs, void* values,
+                      bool zero_fill, diaq_dia** out);
+
+// SpMV operand view of a DiaQ matrix with the given effective flags.
+SpmvOp op_of(const diaq_dia* A, bool transpose, bool conjugate);
+
+}  // namespace diaq

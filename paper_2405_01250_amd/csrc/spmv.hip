@@ -1,0 +1,503 @@
+// spmv.hip -- DiaQ sparse matrix-vector product (Alg. 2) and the fused
+// expectation / generator reductions, for gfx950.
+//
+// Row ownership replaces Alg. 2's loop over diagonals: each lane owns output
+// rows and sums, in ascending diagonal index, D_k(i) * x[i + d_k] over the
+// diagonals whose range covers row i, then stores y[i] once.  There is one
+// writer per y element, so the race of Alg. 2's parallel loop over
+// diagonals (all writing y) cannot occur, no atomics are needed and y is
+// never read or pre-zeroed.
+//
+// Memory plan (the product is HBM-bound, ~0.3 flop/byte in fp64):
+//  * a wave reads 64 consecutive rows, so every diagonal stream and every
+//    shifted x stream is a unit-stride, 16-byte-per-lane coalesced access;
+//  * a value that is exactly zero skips its x load (expanded gates store
+//    explicit zeros on half of each off-principal diagonal, and skipping them
+//    keeps x at one HBM read per element);
+//  * offsets larger than a tile are handled by grouping tiles: one
+//    workgroup owns the tiles {base + sum s_b 2^b} for the gate's high
+//    coupling bits b, so x[i] and x[i +- 2^b] are fetched from HBM once and
+//    re-read from L1/L2 of the same CU (workgroups are spread round-robin
+//    over the 8 XCDs, so sharing across workgroups would not hit one L2).
+#include "internal.hpp"
+
+namespace diaq {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename R>
+struct Vec;
+template <>
+struct Vec<double> {
+  using V = double2;
+};
+template <>
+struct Vec<float> {
+  using V = float2;
+};
+
+struct RowMap {
+  int64_t N;
+  int32_t tile_log2;  // log2(rows per tile)
+  int32_t ng;         // number of group bits (0..3)
+  int32_t gbit[3];    // ascending qubit indices, each >= tile_log2
+};
+
+// Insert a zero bit at each group position (ascending) into v.
+__device__ __forceinline__ int64_t insert_zero_bits(int64_t v, const RowMap& m) {
+  for (int b = 0; b < m.ng; b++) {
+    const int p = m.gbit[b];
+    const int64_t lo = v & ((int64_t(1) << p) - 1);
+    v = lo | ((v >> p) << (p + 1));
+  }
+  return v;
+}
+
+__device__ __forceinline__ int64_t group_offset(int s, const RowMap& m) {
+  int64_t o = 0;
+  for (int b = 0; b < m.ng; b++)
+    if ((s >> b) & 1) o |= int64_t(1) << m.gbit[b];
+  return o;
+}
+
+struct DiagSrc {
+  const int64_t* dmeta;  // device table or nullptr
+  int32_t nd;
+  int32_t transpose;
+  int32_t conjugate;
+};
+
+// (applied offset e, value base vb): row i uses vals[vb + i] * x[i + e].
+__device__ __forceinline__ void diag_at(const DiagArgs& da, const DiagSrc& src, int k,
+                                        int64_t& e, int64_t& vb) {
+  const int kk = src.transpose ? (src.nd - 1 - k) : k;
+  int64_t d, st;
+  if (src.dmeta) {
+    d = src.dmeta[kk];
+    st = src.dmeta[src.nd + kk];
+  } else {
+    d = da.off[kk];
+    st = da.start[kk];
+  }
+  if (src.transpose) {
+    // (A^T) diagonal -d at row i is A's diagonal d at row i - d, whose
+    // compact index is (i - d) + min(0, d) = i - max(0, d).
+    e = -d;
+    vb = st - (d > 0 ? d : 0);
+  } else {
+    e = d;
+    vb = st + (d < 0 ? d : 0);
+  }
+}
+
+template <typename V>
+__device__ __forceinline__ bool nonzero(const V& v) {
+  return v.x != 0 || v.y != 0;
+}
+
+template <typename R>
+__device__ __forceinline__ void cfma(typename Vec<R>::V& acc, const typename Vec<R>::V& a,
+                                     const typename Vec<R>::V& b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+
+// Computes acc[s*RPT + j] = (op(A) x)[row(s, j)] for the G*RPT rows a lane
+// owns; rows outside [0, N) (only when N < tile) are left at zero.
+template <typename R, int RPT, int G, bool CHECK>
+__device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src, const RowMap& m,
+                                         const typename Vec<R>::V* __restrict__ vals,
+                                         const typename Vec<R>::V* __restrict__ x, int64_t base,
+                                         typename Vec<R>::V (&acc)[G * RPT],
+                                         int64_t (&row)[G * RPT]) {
+  using V = typename Vec<R>::V;
+  const int64_t N = m.N;
+#pragma unroll
+  for (int s = 0; s < G; s++)
+#pragma unroll
+    for (int j = 0; j < RPT; j++) {
+      row[s * RPT + j] = base + group_offset(s, m) + j * kBlock + threadIdx.x;
+      acc[s * RPT + j] = V{0, 0};
+    }
+  for (int k = 0; k < src.nd; k++) {
+    int64_t e, vb;
+    diag_at(da, src, k, e, vb);
+    const int64_t lo = e < 0 ? -e : 0;
+    const int64_t hi = e > 0 ? N - e : N;
+    V v[G * RPT];
+#pragma unroll
+    for (int r = 0; r < G * RPT; r++) {
+      const int64_t i = row[r];
+      const bool in = (i >= lo) && (i < hi) && (!CHECK || i < N);
+      v[r] = in ? vals[vb + i] : V{0, 0};
+    }
+    if (src.conjugate) {
+#pragma unroll
+      for (int r = 0; r < G * RPT; r++) v[r].y = -v[r].y;
+    }
+    // issue every x load of this diagonal before the first multiply, so the
+    // loads of all owned rows are in flight together
+    V xv[G * RPT];
+#pragma unroll
+    for (int r = 0; r < G * RPT; r++) {
+      xv[r] = V{0, 0};
+      if (nonzero(v[r])) xv[r] = x[row[r] + e];
+    }
+#pragma unroll
+    for (int r = 0; r < G * RPT; r++) cfma<R>(acc[r], v[r], xv[r]);
+  }
+}
+
+template <typename R, int RPT, int G, bool CHECK>
+__global__ __launch_bounds__(kBlock) void spmv_kernel(DiagArgs da, DiagSrc src, RowMap m,
+                                                      const typename Vec<R>::V* __restrict__ vals,
+                                                      const typename Vec<R>::V* __restrict__ x,
+                                                      typename Vec<R>::V* __restrict__ y) {
+  using V = typename Vec<R>::V;
+  const int64_t base = insert_zero_bits(int64_t(blockIdx.x) << m.tile_log2, m);
+  V acc[G * RPT];
+  int64_t row[G * RPT];
+  dia_rows<R, RPT, G, CHECK>(da, src, m, vals, x, base, acc, row);
+#pragma unroll
+  for (int r = 0; r < G * RPT; r++)
+    if (!CHECK || row[r] < m.N) y[row[r]] = acc[r];
+}
+
+// In-place variant for matrices whose only diagonal is the principal one.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void diag_inplace_kernel(int64_t N, int32_t conjugate,
+                                                              const typename Vec<R>::V* __restrict__ vals,
+                                                              typename Vec<R>::V* xy) {
+  using V = typename Vec<R>::V;
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
+    V v = vals[i];
+    if (conjugate) v.y = -v.y;
+    const V a = xy[i];
+    V r{0, 0};
+    cfma<R>(r, v, a);
+    xy[i] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: per-workgroup partial sums in fixed order, then one pass.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void block_reduce_store(double re, double im, double2* partial) {
+  // wave64 butterfly
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  __shared__ double2 wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) wsum[wave] = double2{re, im};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 t = wsum[0];
+    for (int w = 1; w < kBlock / 64; w++) {
+      t.x += wsum[w].x;
+      t.y += wsum[w].y;
+    }
+    partial[blockIdx.x] = t;
+  }
+}
+
+template <typename R, int RPT, int G, bool CHECK>
+__global__ __launch_bounds__(kBlock) void expect_kernel(DiagArgs da, DiagSrc src, RowMap m,
+                                                        const typename Vec<R>::V* __restrict__ vals,
+                                                        const typename Vec<R>::V* __restrict__ psi,
+                                                        const typename Vec<R>::V* __restrict__ phi,
+                                                        double2* __restrict__ partial) {
+  using V = typename Vec<R>::V;
+  const int64_t base = insert_zero_bits(int64_t(blockIdx.x) << m.tile_log2, m);
+  V acc[G * RPT];
+  int64_t row[G * RPT];
+  dia_rows<R, RPT, G, CHECK>(da, src, m, vals, phi, base, acc, row);
+  double re = 0, im = 0;
+#pragma unroll
+  for (int r = 0; r < G * RPT; r++) {
+    if (CHECK && row[r] >= m.N) continue;
+    const V p = psi[row[r]];
+    // conj(p) * acc
+    re += double(p.x) * double(acc[r].x) + double(p.y) * double(acc[r].y);
+    im += double(p.x) * double(acc[r].y) - double(p.y) * double(acc[r].x);
+  }
+  block_reduce_store(re, im, partial);
+}
+
+// One workgroup sums partial[0..count) in a fixed order.
+__global__ __launch_bounds__(1024) void final_reduce_kernel(const double2* __restrict__ partial,
+                                                            int64_t count, double2* __restrict__ out) {
+  double re = 0, im = 0;
+  for (int64_t i = threadIdx.x; i < count; i += 1024) {
+    re += partial[i].x;
+    im += partial[i].y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  __shared__ double2 wsum[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) wsum[wave] = double2{re, im};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 t = wsum[0];
+    for (int w = 1; w < 16; w++) {
+      t.x += wsum[w].x;
+      t.y += wsum[w].y;
+    }
+    *out = t;
+  }
+}
+
+// <lam | G | psi> where G acts on k target qubits (local matrix gm) and is
+// zero wherever a control bit is 0.  Each lane owns one coset of 2^k
+// amplitudes (the target bits enumerate it), so lam and psi are read once.
+struct GenArgs {
+  int64_t ncos;         // number of cosets = N / 2^k
+  int32_t k;
+  int32_t tq[3];        // target qubits, ascending order of local bit
+  int32_t sorted_t[3];  // target qubits sorted ascending (for insertion)
+  uint64_t cmask;
+  double g[8][8][2];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void generator_dot_kernel(GenArgs a,
+                                                               const typename Vec<R>::V* __restrict__ lam,
+                                                               const typename Vec<R>::V* __restrict__ psi,
+                                                               double2* __restrict__ partial) {
+  using V = typename Vec<R>::V;
+  double re = 0, im = 0;
+  const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (c < a.ncos) {
+    int64_t b = c;
+    for (int j = 0; j < a.k; j++) {
+      const int p = a.sorted_t[j];
+      b = (b & ((int64_t(1) << p) - 1)) | ((b >> p) << (p + 1));
+    }
+    if ((uint64_t(b) & a.cmask) == a.cmask) {
+      const int d = 1 << a.k;
+      int64_t idx[8];
+      double pr[8], pi[8];
+      for (int r = 0; r < d; r++) {
+        int64_t o = 0;
+        for (int j = 0; j < a.k; j++)
+          if ((r >> j) & 1) o |= int64_t(1) << a.tq[j];
+        idx[r] = b + o;
+        const V p = psi[idx[r]];
+        pr[r] = p.x;
+        pi[r] = p.y;
+      }
+      for (int r = 0; r < d; r++) {
+        double gr = 0, gi = 0;
+        for (int cc = 0; cc < d; cc++) {
+          const double mr = a.g[r][cc][0], mi = a.g[r][cc][1];
+          gr += mr * pr[cc] - mi * pi[cc];
+          gi += mr * pi[cc] + mi * pr[cc];
+        }
+        const V l = lam[idx[r]];
+        re += double(l.x) * gr + double(l.y) * gi;
+        im += double(l.x) * gi - double(l.y) * gr;
+      }
+    }
+  }
+  block_reduce_store(re, im, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Host planning
+// ---------------------------------------------------------------------------
+
+struct Plan {
+  RowMap map;
+  int rpt;
+  int g;
+  bool check;
+  int64_t blocks;
+};
+
+Plan plan_rows(const SpmvOp& op, int rpt_hint) {
+  Plan p{};
+  const int n = op.n;
+  p.map.N = int64_t(1) << n;
+  int rpt = rpt_hint > 0 ? rpt_hint : 2;
+  if (rpt != 1 && rpt != 2 && rpt != 4) rpt = 2;
+  int tile_log2 = 8 + (rpt == 4 ? 2 : rpt == 2 ? 1 : 0);
+  if (n < tile_log2) {
+    // tiny matrix: one row per lane, bounds-checked
+    p.rpt = 1;
+    p.g = 1;
+    p.check = true;
+    p.map.tile_log2 = 8;
+    p.map.ng = 0;
+    p.blocks = (p.map.N + kBlock - 1) / kBlock;
+    return p;
+  }
+  // group the highest coupling bits at or above the tile size
+  int bits[64], nb = 0;
+  for (int q = n - 1; q >= tile_log2 && nb < 3; q--)
+    if ((op.qubit_mask >> q) & 1) bits[nb++] = q;
+  // G = 8 with 2 rows per lane is 16 live accumulators; drop to 1 row.
+  if (nb == 3 && rpt > 1) {
+    rpt = 1;
+    tile_log2 = 8;
+  }
+  p.rpt = rpt;
+  p.map.tile_log2 = tile_log2;
+  p.map.ng = nb;
+  for (int b = 0; b < nb; b++) p.map.gbit[b] = bits[nb - 1 - b];  // ascending
+  p.g = 1 << nb;
+  p.check = false;
+  p.blocks = p.map.N >> (tile_log2 + nb);
+  return p;
+}
+
+template <typename R>
+diaq_status_t launch_typed(diaq_ctx* ctx, const SpmvOp& op, const DiagArgs& da, const DiagSrc& src,
+                           const Plan& p, const void* vals, const void* x, void* y, double2* partial,
+                           const void* psi) {
+  using V = typename Vec<R>::V;
+  const V* v = static_cast<const V*>(vals);
+  const V* xx = static_cast<const V*>(x);
+  dim3 grid(unsigned(p.blocks)), block(kBlock);
+#define DIAQ_LAUNCH(RPT, G, CHK)                                                                 \
+  do {                                                                                           \
+    if (partial)                                                                                 \
+      hipLaunchKernelGGL((expect_kernel<R, RPT, G, CHK>), grid, block, 0, ctx->stream, da, src,  \
+                         p.map, v, static_cast<const V*>(psi), xx, partial);                     \
+    else                                                                                         \
+      hipLaunchKernelGGL((spmv_kernel<R, RPT, G, CHK>), grid, block, 0, ctx->stream, da, src,    \
+                         p.map, v, xx, static_cast<V*>(y));                                      \
+  } while (0)
+  if (p.check) {
+    DIAQ_LAUNCH(1, 1, true);
+  } else if (p.g == 1) {
+    if (p.rpt == 4) DIAQ_LAUNCH(4, 1, false);
+    else if (p.rpt == 2) DIAQ_LAUNCH(2, 1, false);
+    else DIAQ_LAUNCH(1, 1, false);
+  } else if (p.g == 2) {
+    if (p.rpt == 4) DIAQ_LAUNCH(4, 2, false);
+    else if (p.rpt == 2) DIAQ_LAUNCH(2, 2, false);
+    else DIAQ_LAUNCH(1, 2, false);
+  } else if (p.g == 4) {
+    if (p.rpt == 2) DIAQ_LAUNCH(2, 4, false);
+    else DIAQ_LAUNCH(1, 4, false);
+  } else {
+    DIAQ_LAUNCH(1, 8, false);
+  }
+#undef DIAQ_LAUNCH
+  DIAQ_HIP(hipGetLastError());
+  return DIAQ_OK;
+}
+
+diaq_status_t prepare(const SpmvOp& op, DiagArgs& da, DiagSrc& src) {
+  std::memset(&da, 0, sizeof(da));
+  src.nd = op.nd;
+  src.transpose = op.transpose ? 1 : 0;
+  src.conjugate = op.conjugate ? 1 : 0;
+  if (op.nd <= kMaxArgDiags) {
+    src.dmeta = nullptr;
+    da.nd = op.nd;
+    for (int k = 0; k < op.nd; k++) {
+      da.off[k] = op.host_off[k];
+      da.start[k] = op.host_start[k];
+    }
+  } else {
+    if (!op.dmeta) return fail(DIAQ_ERR_INVALID_ARGUMENT, "matrix with %d diagonals has no device table", op.nd);
+    src.dmeta = op.dmeta;
+    da.nd = 0;
+  }
+  return DIAQ_OK;
+}
+
+}  // namespace
+
+diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* y) {
+  const int64_t N = int64_t(1) << op.n;
+  if (op.nd == 0) {
+    DIAQ_HIP(hipMemsetAsync(y, 0, size_t(N) * elem_bytes(op.dtype), ctx->stream));
+    return DIAQ_OK;
+  }
+  if (x == y) {
+    // only a principal-diagonal-only matrix may run in place
+    if (!(op.nd == 1 && op.host_off[0] == 0))
+      return fail(DIAQ_ERR_INVALID_ARGUMENT, "x and y alias for a matrix with off-principal diagonals");
+    const int64_t blocks = std::min<int64_t>((N + kBlock - 1) / kBlock, int64_t(ctx->num_cus) * 64);
+    if (op.dtype == DIAQ_C128)
+      hipLaunchKernelGGL(diag_inplace_kernel<double>, dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream, N,
+                         op.conjugate ? 1 : 0, static_cast<const double2*>(op.values), static_cast<double2*>(y));
+    else
+      hipLaunchKernelGGL(diag_inplace_kernel<float>, dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream, N,
+                         op.conjugate ? 1 : 0, static_cast<const float2*>(op.values), static_cast<float2*>(y));
+    DIAQ_HIP(hipGetLastError());
+    return DIAQ_OK;
+  }
+  DiagArgs da;
+  DiagSrc src;
+  DIAQ_TRY(prepare(op, da, src));
+  const Plan p = plan_rows(op, ctx->spmv_rows);
+  if (op.dtype == DIAQ_C128) return launch_typed<double>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
+  return launch_typed<float>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
+}
+
+static diaq_status_t final_reduce(diaq_ctx* ctx, const double2* partial, int64_t count, double* dres) {
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(1024), 0, ctx->stream, partial, count,
+                     reinterpret_cast<double2*>(dres));
+  DIAQ_HIP(hipGetLastError());
+  return DIAQ_OK;
+}
+
+diaq_status_t launch_expect(diaq_ctx* ctx, const SpmvOp& op, const void* psi, const void* phi, double* dres) {
+  if (op.nd == 0) {
+    DIAQ_HIP(hipMemsetAsync(dres, 0, 2 * sizeof(double), ctx->stream));
+    return DIAQ_OK;
+  }
+  DiagArgs da;
+  DiagSrc src;
+  DIAQ_TRY(prepare(op, da, src));
+  const Plan p = plan_rows(op, ctx->spmv_rows);
+  DIAQ_TRY(ensure(ctx, &ctx->red, size_t(p.blocks) * sizeof(double2)));
+  double2* partial = static_cast<double2*>(ctx->red.ptr);
+  if (op.dtype == DIAQ_C128)
+    DIAQ_TRY(launch_typed<double>(ctx, op, da, src, p, op.values, phi, nullptr, partial, psi));
+  else
+    DIAQ_TRY(launch_typed<float>(ctx, op, da, src, p, op.values, phi, nullptr, partial, psi));
+  return final_reduce(ctx, partial, p.blocks, dres);
+}
+
+diaq_status_t launch_generator_dot(diaq_ctx* ctx, const LocalGate& gen, int n, diaq_dtype_t dt,
+                                   const void* lam, const void* psi, double* dres) {
+  GenArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.k = gen.k;
+  a.ncos = (int64_t(1) << n) >> gen.k;
+  for (int j = 0; j < gen.k; j++) a.tq[j] = gen.targets[j];
+  int st[3] = {gen.targets[0], gen.targets[1], gen.targets[2]};
+  std::sort(st, st + gen.k);
+  for (int j = 0; j < gen.k; j++) a.sorted_t[j] = st[j];
+  a.cmask = gen.cmask;
+  std::memcpy(a.g, gen.m, sizeof(a.g));
+  const int64_t blocks = (a.ncos + kBlock - 1) / kBlock;
+  DIAQ_TRY(ensure(ctx, &ctx->red, size_t(blocks) * sizeof(double2)));
+  double2* partial = static_cast<double2*>(ctx->red.ptr);
+  if (dt == DIAQ_C128)
+    hipLaunchKernelGGL(generator_dot_kernel<double>, dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream, a,
+                       static_cast<const double2*>(lam), static_cast<const double2*>(psi), partial);
+  else
+    hipLaunchKernelGGL(generator_dot_kernel<float>, dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream, a,
+                       static_cast<const float2*>(lam), static_cast<const float2*>(psi), partial);
+  DIAQ_HIP(hipGetLastError());
+  return final_reduce(ctx, partial, blocks, dres);
+}
+
+}  // namespace diaq

@@ -1,0 +1,444 @@
+"""ctypes binding of libdiaq_hip (the C ABI in ``include/diaq.h``).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of ``libdiaq_hip.so``.  PyTorch supplies device memory (tensors'
+``data_ptr``) and the HIP stream (torch's current stream).  There is no CPU
+fallback: if the library or a GPU is missing, calls raise.
+
+Function names follow the C ABI: ``from_gate``, ``from_pauli_sum``,
+``spmv``, ``fuse``, ``apply_circuit``, ``expect``, ``adjoint_grad``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdiaq_hip.so")
+
+C64, C128 = 0, 1
+TRANSPOSE, CONJUGATE, ADJOINT = 1, 2, 3
+
+GATE_KINDS = {"I": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8, "SX": 9,
+              "RX": 10, "RY": 11, "RZ": 12, "P": 13, "U3": 14, "SWAP": 15, "RXX": 16, "RYY": 17,
+              "RZZ": 18, "MATRIX": 19}
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "not multiplyable", 3: "out of memory",
+          4: "device error", 5: "unsupported"}
+
+
+class DiaqError(RuntimeError):
+    """A libdiaq_hip call returned a non-zero status."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS.get(status, "status %d" % status), message))
+        self.status = status
+
+
+class diaq_gate_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ntargets", ctypes.c_int32), ("ncontrols", ctypes.c_int32),
+                ("targets", ctypes.c_int32 * 3), ("controls", ctypes.c_int32 * 3),
+                ("params", ctypes.c_double * 3), ("param_index", ctypes.c_int32),
+                ("param_scale", ctypes.c_double), ("matrix", ctypes.POINTER(ctypes.c_double))]
+
+
+class diaq_plan_t(ctypes.Structure):
+    _fields_ = [("fuse", ctypes.c_int32), ("max_fused_qubits", ctypes.c_int32), ("kron", ctypes.c_int32),
+                ("rows_per_thread", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_D = ctypes.c_double
+
+# name -> argtypes (restype is int status unless noted)
+_SIGS = {
+    "diaq_create": [_I32, _P, ctypes.POINTER(_P)],
+    "diaq_set_stream": [_P, _P],
+    "diaq_synchronize": [_P],
+    "diaq_destroy": [_P],
+    "diaq_dia_create": [_P, _I32, _I32, _I32, ctypes.POINTER(_I64), _P, ctypes.POINTER(_P)],
+    "diaq_dia_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                      ctypes.POINTER(_I64), ctypes.POINTER(_P)],
+    "diaq_dia_offsets": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
+    "diaq_dia_transpose": [_P, _I32, ctypes.POINTER(_P)],
+    "diaq_dia_copy_values": [_P, _P, _P, _I32],
+    "diaq_dia_free": [_P],
+    "diaq_from_gate_query": [ctypes.POINTER(diaq_gate_t), _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I64),
+                             ctypes.POINTER(_I64)],
+    "diaq_from_gate": [_P, ctypes.POINTER(diaq_gate_t), _I32, _I32, ctypes.POINTER(_P)],
+    "diaq_from_pauli_sum": [_P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_uint64),
+                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_D), ctypes.POINTER(_P)],
+    "diaq_spmv": [_P, _P, _P, _P, _U32],
+    "diaq_fuse": [_P, _P, _P, _D, ctypes.POINTER(_P)],
+    "diaq_apply_circuit": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I64, _I64, _I32, _I32, _P, _P,
+                           ctypes.POINTER(diaq_plan_t)],
+    "diaq_expect": [_P, _P, _P, _P, ctypes.POINTER(_D)],
+    "diaq_adjoint_grad": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _P, _P, _P, _I64,
+                          ctypes.POINTER(_D), ctypes.POINTER(_D)],
+}
+
+EXPORTED = sorted(_SIGS) + ["diaq_last_error", "diaq_status_string"]
+
+
+def load(path: str = LIB_PATH):
+    """Open libdiaq_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libdiaq_hip.so not built at %s; run __graft_entry__.build()" % path)
+        lib = ctypes.CDLL(path)
+        for name, args in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.diaq_last_error.restype = ctypes.c_char_p
+        lib.diaq_last_error.argtypes = []
+        lib.diaq_status_string.restype = ctypes.c_char_p
+        lib.diaq_status_string.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise DiaqError(status, load().diaq_last_error().decode(errors="replace"))
+
+
+# --------------------------------------------------------------------------
+# Contexts (one per device and torch stream)
+# --------------------------------------------------------------------------
+
+_contexts: dict = {}
+
+
+class Context:
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+        h = _P()
+        _check(load().diaq_create(device, _P(self.stream), ctypes.byref(h)))
+        self.handle = h
+
+    def synchronize(self):
+        _check(load().diaq_synchronize(self.handle))
+
+    def close(self):
+        if self.handle:
+            load().diaq_destroy(self.handle)
+            self.handle = None
+
+
+def context(device: int | None = None) -> Context:
+    """The context bound to torch's current stream on `device`."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("libdiaq_hip needs a HIP GPU; none is visible")
+    if device is None:
+        device = torch.cuda.current_device()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    key = (device, stream)
+    ctx = _contexts.get(key)
+    if ctx is None:
+        ctx = Context(device, stream)
+        _contexts[key] = ctx
+    return ctx
+
+
+# --------------------------------------------------------------------------
+# Gates
+# --------------------------------------------------------------------------
+
+def _dtype_code(dtype) -> int:
+    if dtype in (torch.complex128, np.complex128, "c128", C128):
+        return C128
+    if dtype in (torch.complex64, np.complex64, "c64", C64):
+        return C64
+    raise ValueError("unsupported dtype %r (complex64 or complex128)" % (dtype,))
+
+
+def _torch_dtype(code: int):
+    return torch.complex128 if code == C128 else torch.complex64
+
+
+def gate_struct(g, keep: list) -> diaq_gate_t:
+    """Marshal one gate object (kind, targets, controls, params,
+    param_index, param_scale, matrix)."""
+    s = diaq_gate_t()
+    s.kind = GATE_KINDS[g.kind]
+    t = tuple(g.targets)
+    c = tuple(getattr(g, "controls", ()) or ())
+    if len(t) > 3 or len(c) > 3:
+        raise DiaqError(1, "a gate takes at most 3 targets and 3 controls")
+    s.ntargets, s.ncontrols = len(t), len(c)
+    for j, q in enumerate(t):
+        s.targets[j] = q
+    for j, q in enumerate(c):
+        s.controls[j] = q
+    for j, p in enumerate(tuple(getattr(g, "params", ()) or ())):
+        s.params[j] = float(p)
+    s.param_index = int(getattr(g, "param_index", -1))
+    s.param_scale = float(getattr(g, "param_scale", 1.0))
+    m = getattr(g, "matrix", None)
+    if m is not None:
+        arr = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+        keep.append(arr)
+        s.matrix = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return s
+
+
+def gate_array(gates: Sequence):
+    keep: list = []
+    arr = (diaq_gate_t * max(1, len(gates)))()
+    for i, g in enumerate(gates):
+        arr[i] = gate_struct(g, keep)
+    return arr, keep
+
+
+# --------------------------------------------------------------------------
+# DiaQ matrices
+# --------------------------------------------------------------------------
+
+class DiaqMatrix:
+    """Handle to a DiaQ matrix living in device memory (Sec. IV)."""
+
+    def __init__(self, handle, ctx: Context, owner=None):
+        self.handle = handle
+        self.ctx = ctx
+        self._owner = owner  # keeps shared storage alive (transpose views)
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.diaq_dia_free(self.handle)
+        except Exception:
+            pass
+        self.handle = None
+
+    def info(self):
+        n, nd, dt, nv = _I32(), _I32(), _I32(), _I64()
+        vp = _P()
+        _check(load().diaq_dia_info(self.handle, ctypes.byref(n), ctypes.byref(nd), ctypes.byref(dt),
+                                    ctypes.byref(nv), ctypes.byref(vp)))
+        return n.value, nd.value, dt.value, nv.value, vp.value
+
+    @property
+    def nqubits(self) -> int:
+        return self.info()[0]
+
+    @property
+    def ndiag(self) -> int:
+        return self.info()[1]
+
+    @property
+    def dtype(self):
+        return _torch_dtype(self.info()[2])
+
+    def offsets(self) -> np.ndarray:
+        nd = self.ndiag
+        o = np.zeros(max(nd, 1), dtype=np.int64)
+        s = np.zeros(nd + 1, dtype=np.int64)
+        _check(load().diaq_dia_offsets(self.handle, o.ctypes.data_as(ctypes.POINTER(_I64)),
+                                       s.ctypes.data_as(ctypes.POINTER(_I64))))
+        return o[:nd]
+
+    def stored_offsets(self):
+        return self.offsets()
+
+    def values(self) -> np.ndarray:
+        """Host copy of the stored (packed) diagonals."""
+        n, nd, dt, nv, _ = self.info()
+        out = np.zeros(nv, dtype=np.complex128 if dt == C128 else np.complex64)
+        if nv:
+            _check(load().diaq_dia_copy_values(self.ctx.handle, self.handle, _P(out.ctypes.data), 1))
+        return out
+
+    def diagonals(self) -> dict:
+        """{dIndex: compact diagonal} as applied (transposed views relabelled)."""
+        n, nd, dt, nv, _ = self.info()
+        vals = self.values()
+        o = np.zeros(max(nd, 1), dtype=np.int64)
+        s = np.zeros(nd + 1, dtype=np.int64)
+        _check(load().diaq_dia_offsets(self.handle, o.ctypes.data_as(ctypes.POINTER(_I64)),
+                                       s.ctypes.data_as(ctypes.POINTER(_I64))))
+        N = 1 << n
+        out = {}
+        for k in range(nd):
+            d = int(o[k])
+            out[d] = vals[s[k]:s[k] + N - abs(d)]
+        return out
+
+    def transpose(self, conjugate: bool = False) -> "DiaqMatrix":
+        h = _P()
+        _check(load().diaq_dia_transpose(self.handle, 1 if conjugate else 0, ctypes.byref(h)))
+        return DiaqMatrix(h, self.ctx, owner=self)
+
+
+def dia_create(n: int, offsets: Iterable[int], values: torch.Tensor | None = None, dtype=torch.complex128,
+               ctx: Context | None = None) -> DiaqMatrix:
+    """Wrap caller-filled packed diagonals (a device tensor, kept alive by
+    the returned handle) or allocate zeroed ones."""
+    ctx = ctx or context()
+    offs = np.ascontiguousarray(np.asarray(list(offsets), dtype=np.int64))
+    h = _P()
+    vp = None
+    if values is not None:
+        if not values.is_cuda or not values.is_contiguous():
+            raise ValueError("values must be a contiguous device tensor")
+        dtype = values.dtype
+        vp = _P(values.data_ptr())
+    _check(load().diaq_dia_create(ctx.handle, n, _dtype_code(dtype), len(offs),
+                                  offs.ctypes.data_as(ctypes.POINTER(_I64)), vp, ctypes.byref(h)))
+    return DiaqMatrix(h, ctx, owner=values)
+
+
+def from_dense_diagonals(n: int, diags: dict, dtype=torch.complex128, ctx: Context | None = None) -> DiaqMatrix:
+    """numpy -> DiaQ converter: {dIndex: compact diagonal} to a device matrix."""
+    offs = sorted(diags)
+    packed = np.concatenate([np.asarray(diags[d]) for d in offs]) if offs else np.zeros(0)
+    t = torch.from_numpy(np.ascontiguousarray(packed.astype(np.complex128 if dtype == torch.complex128
+                                                            else np.complex64))).to("cuda")
+    return dia_create(n, offs, t if t.numel() else None, dtype, ctx)
+
+
+def from_gate_query(gate, n: int):
+    keep: list = []
+    s = gate_struct(gate, keep)
+    nd = _I32()
+    offs = np.zeros(27, dtype=np.int64)
+    nv = _I64()
+    _check(load().diaq_from_gate_query(ctypes.byref(s), n, ctypes.byref(nd),
+                                       offs.ctypes.data_as(ctypes.POINTER(_I64)), ctypes.byref(nv)))
+    return offs[:nd.value].copy(), nv.value
+
+
+def from_gate(gate, n: int, dtype=torch.complex128, ctx: Context | None = None) -> DiaqMatrix:
+    ctx = ctx or context()
+    keep: list = []
+    s = gate_struct(gate, keep)
+    h = _P()
+    _check(load().diaq_from_gate(ctx.handle, ctypes.byref(s), n, _dtype_code(dtype), ctypes.byref(h)))
+    return DiaqMatrix(h, ctx)
+
+
+def from_pauli_sum(n: int, terms, dtype=torch.complex128, ctx: Context | None = None) -> DiaqMatrix:
+    """terms = [(xmask, zmask, coef)], term = coef * i^{|x&z|} X^x Z^z."""
+    ctx = ctx or context()
+    xs = np.ascontiguousarray(np.array([t[0] for t in terms], dtype=np.uint64))
+    zs = np.ascontiguousarray(np.array([t[1] for t in terms], dtype=np.uint64))
+    cs = np.ascontiguousarray(np.array([t[2] for t in terms], dtype=np.float64))
+    h = _P()
+    _check(load().diaq_from_pauli_sum(ctx.handle, n, _dtype_code(dtype), len(terms),
+                                      xs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      zs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      cs.ctypes.data_as(ctypes.POINTER(_D)), ctypes.byref(h)))
+    return DiaqMatrix(h, ctx)
+
+
+# --------------------------------------------------------------------------
+# Kernels
+# --------------------------------------------------------------------------
+
+def _vec(t: torch.Tensor, n: int, dtype_code: int, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous() or t.numel() != (1 << n) or _dtype_code(t.dtype) != dtype_code:
+        raise ValueError("%s must be a contiguous %s vector of 2^%d elements" % (name, _torch_dtype(dtype_code), n))
+    return _P(t.data_ptr())
+
+
+def spmv(A: DiaqMatrix, x: torch.Tensor, y: torch.Tensor | None = None, flags: int = 0) -> torch.Tensor:
+    """y <- op(A) x (Alg. 2)."""
+    n, _, dt, _, _ = A.info()
+    if y is None:
+        y = torch.empty_like(x)
+    _check(load().diaq_spmv(A.ctx.handle, A.handle, _vec(x, n, dt, "x"), _vec(y, n, dt, "y"), flags))
+    return y
+
+
+def fuse(first: DiaqMatrix, second: DiaqMatrix, drop_tol: float = 0.0) -> DiaqMatrix:
+    """second * first (Alg. 1)."""
+    h = _P()
+    _check(load().diaq_fuse(first.ctx.handle, first.handle, second.handle, drop_tol, ctypes.byref(h)))
+    return DiaqMatrix(h, first.ctx)
+
+
+def make_plan(fuse: bool = False, max_fused_qubits: int = 0, kron: bool = False, rows_per_thread: int = 0,
+              block: int = 0) -> diaq_plan_t:
+    p = diaq_plan_t()
+    p.fuse, p.max_fused_qubits, p.kron = int(fuse), max_fused_qubits, int(kron)
+    p.rows_per_thread, p.block = rows_per_thread, block
+    return p
+
+
+def apply_circuit(gates: Sequence, state: torch.Tensor, n: int | None = None, scratch: torch.Tensor | None = None,
+                  plan: diaq_plan_t | None = None, begin: int = 0, end: int | None = None,
+                  ctx: Context | None = None, marshalled=None) -> torch.Tensor:
+    """In place: state <- U_{end-1} ... U_begin state."""
+    ctx = ctx or context(state.device.index)
+    if n is None:
+        n = int(state.numel()).bit_length() - 1
+    dt = _dtype_code(state.dtype)
+    if scratch is None:
+        scratch = torch.empty_like(state)
+    arr, keep = marshalled if marshalled is not None else gate_array(gates)
+    ng = len(gates)
+    e = ng if end is None else end
+    _check(load().diaq_apply_circuit(ctx.handle, arr, ng, begin, e, n, dt, _vec(state, n, dt, "state"),
+                                     _vec(scratch, n, dt, "scratch"),
+                                     ctypes.byref(plan) if plan is not None else None))
+    return state
+
+
+def expect(H: DiaqMatrix, psi: torch.Tensor, phi: torch.Tensor | None = None) -> complex:
+    """<psi|H|phi> (phi defaults to psi); synchronises the stream."""
+    n, _, dt, _, _ = H.info()
+    out = (_D * 2)()
+    _check(load().diaq_expect(H.ctx.handle, H.handle, _vec(psi, n, dt, "psi"),
+                              _vec(phi, n, dt, "phi") if phi is not None else None, out))
+    return complex(out[0], out[1])
+
+
+def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: int,
+                 work: torch.Tensor | None = None):
+    """(E, dE/dtheta) by the adjoint reverse sweep; synchronises."""
+    n, _, dt, _, _ = H.info()
+    if work is None:
+        work = torch.empty(3 << n, dtype=psi0.dtype, device=psi0.device)
+    if work.numel() < (3 << n) or work.dtype != psi0.dtype or not work.is_contiguous():
+        raise ValueError("work must hold 3 * 2^n contiguous elements of the state dtype")
+    arr, keep = gate_array(gates)
+    e = _D()
+    grad = np.zeros(max(nparams, 1), dtype=np.float64)
+    _check(load().diaq_adjoint_grad(H.ctx.handle, arr, len(gates), n, dt, H.handle, _vec(psi0, n, dt, "psi0"),
+                                    _P(work.data_ptr()), nparams, ctypes.byref(e),
+                                    grad.ctypes.data_as(ctypes.POINTER(_D))))
+    return e.value, grad[:nparams]
+
+
+class DiaqExpectation(torch.autograd.Function):
+    """E(theta) = <psi(theta)|H|psi(theta)> with the adjoint backward.
+
+    ``build(theta_list) -> gates`` rebuilds the circuit from the parameter
+    values (gates carry param_index / param_scale)."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, build, H: DiaqMatrix, psi0: torch.Tensor):
+        th = theta.detach().cpu().double().numpy()
+        gates = build(th)
+        e, g = adjoint_grad(gates, H, psi0, th.size)
+        ctx.save_for_backward(torch.from_numpy(g).to(theta.dtype))
+        return torch.tensor(e, dtype=theta.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out * g, None, None, None

@@ -1,0 +1,111 @@
+"""The C ABI library loads and exports every entry point that include/diaq.h
+declares; host-only entry points work without a GPU.  CPU only."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2405_01250_amd import diaq as D
+from paper_2405_01250_amd import inputs as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "diaq.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(diaq_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(D.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return D.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ["diaq_from_gate", "diaq_spmv", "diaq_fuse", "diaq_apply_circuit", "diaq_expect",
+                     "diaq_adjoint_grad"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", D.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT\s+(diaq_[a-z0-9_]+)", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    for n in _declared():
+        assert hasattr(lib, n)
+    # the binding knows every declared entry point
+    assert set(_declared()) <= set(D.EXPORTED)
+
+
+def test_no_torch_types_in_header():
+    text = open(HEADER).read()
+    assert "torch" not in text.lower().replace("torch's", "")
+    assert "at::" not in text and "Tensor" not in text
+
+
+def test_from_gate_query_offsets_fig2(lib):
+    # Fig. 2: Hadamard on each qubit of 4 -> diagonals 0, +-2^q (host-only call)
+    for q in range(4):
+        offs, nv = D.from_gate_query(W.h(q), 4)
+        assert offs.tolist() == [-(1 << q), 0, 1 << q]
+        assert nv == 3 * 16 - 2 * (1 << q)
+
+
+def test_from_gate_query_kinds(lib):
+    n = 6
+    cases = [
+        (W.Gate("Z", (2,)), [0]),
+        (W.Gate("RZ", (1,), (), (0.3,)), [0]),
+        (W.cz(1, 4), [0]),
+        (W.cp(0.4, 0, 5), [0]),
+        (W.Gate("RZZ", (1, 3), (), (0.2,)), [0]),
+        (W.Gate("X", (3,)), [-8, 8]),
+        (W.Gate("Y", (0,)), [-1, 1]),
+        (W.cx(0, 3), [-8, 0, 8]),
+        (W.swap(1, 4), [-14, 0, 14]),
+        (W.Gate("RXX", (0, 2), (), (0.5,)), [-5, -3, 0, 3, 5]),
+        (W.u3(0.1, 0.2, 0.3, 5), [-32, 0, 32]),
+    ]
+    for g, want in cases:
+        offs, _ = D.from_gate_query(g, n)
+        assert offs.tolist() == want, g
+
+
+def test_from_gate_query_rejects_bad_gates(lib):
+    bad = [
+        W.Gate("H", (6,)),                 # qubit out of range
+        W.Gate("SWAP", (1, 1)),            # duplicate qubit
+        W.Gate("X", (2,), (2,)),           # control == target
+        W.Gate("H", (0, 1)),               # wrong target count
+        W.Gate("X", (0,), (1, 2, 3, 4)),   # too many controls
+    ]
+    for g in bad:
+        with pytest.raises(D.DiaqError) as ei:
+            D.from_gate_query(g, 6)
+        assert ei.value.status == 1
+    with pytest.raises(D.DiaqError):
+        D.from_gate_query(W.Gate("MATRIX", (0,)), 4)  # matrix missing
+
+
+def test_create_without_gpu_fails_loudly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = ctypes.c_void_p()
+    st = lib.diaq_create(0, None, ctypes.byref(h))
+    assert st != 0
+    with pytest.raises(RuntimeError):
+        D.context()

@@ -1,0 +1,184 @@
+"""GPU parity of circuit-level entry points (apply_circuit, adjoint_grad)
+against the CPU oracle and closed forms, through the C ABI."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2405_01250_amd import diaq as D
+from paper_2405_01250_amd import inputs as W
+from tests.gpu_util import assert_state_close, to_dev, to_host
+from tests.test_gpu_kernels import _random_gate
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.mark.parametrize("n", [2, 5, 12])
+def test_ghz_closed_form_and_oracle(n):
+    psi = to_dev(W.zero_state(n))
+    D.apply_circuit(W.ghz(n), psi)
+    got = to_host(psi)
+    want = np.zeros(1 << n, dtype=complex)
+    want[0] = want[-1] = 1 / math.sqrt(2)
+    assert_state_close(got, want, TOL64, "GHZ-%d" % n)
+    assert_state_close(got, orc.apply_circuit(W.zero_state(n), n, W.ghz(n)), TOL64)
+
+
+@pytest.mark.parametrize("n", [3, 8, 12, 16])
+def test_qft_matches_oracle_and_ifft(n):
+    x = W.random_state(n, 24)
+    psi = to_dev(x)
+    D.apply_circuit(W.qft(n), psi)
+    got = to_host(psi)
+    assert_state_close(got, orc.apply_circuit(x, n, W.qft(n)), TOL64, "QFT-%d vs oracle" % n)
+    assert_state_close(got, np.fft.ifft(x, norm="ortho"), TOL64, "QFT-%d vs ifft" % n)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_circuits_match_oracle(seed):
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(1, 15))
+    gates = [_random_gate(rng, n) for _ in range(int(rng.integers(1, 40)))]
+    x = W.random_state(n, seed)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi)
+    assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "seed %d n %d" % (seed, n))
+
+
+@pytest.mark.parametrize("n,layers", [(12, 4), (16, 3), (20, 2)])
+def test_random_layered_c128_and_c64(n, layers):
+    gates = W.random_layered(n, layers, n)
+    x = W.zero_state(n)
+    ref = orc.apply_circuit(x, n, gates)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi)
+    assert_state_close(to_host(psi), ref, TOL64, "c128")
+    psi32 = to_dev(x, torch.complex64)
+    D.apply_circuit(gates, psi32)
+    assert_state_close(to_host(psi32), ref, TOL32, "c64", l2tol=1e-4)
+
+
+def test_resume_from_gate_index():
+    n = 10
+    gates = W.random_layered(n, 3, 1)
+    x = W.random_state(n, 2)
+    full = to_dev(x)
+    D.apply_circuit(gates, full)
+    part = to_dev(x)
+    arr = D.gate_array(gates)
+    D.apply_circuit(gates, part, end=17, marshalled=arr)
+    saved = part.clone()
+    D.apply_circuit(gates, saved, begin=17, marshalled=arr)
+    assert torch.equal(saved, full)
+
+
+def test_repeat_runs_bitwise_equal():
+    n = 18
+    gates = W.random_layered(n, 2, 5)
+    outs = []
+    for _ in range(2):
+        psi = to_dev(W.zero_state(n))
+        D.apply_circuit(gates, psi)
+        outs.append(psi)
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_apply_circuit_errors_leave_state_untouched():
+    n = 6
+    x = to_dev(W.random_state(n, 4))
+    before = x.clone()
+    with pytest.raises(D.DiaqError):
+        D.apply_circuit([W.h(0), W.Gate("H", (7,))], x)
+    with pytest.raises(D.DiaqError):
+        D.apply_circuit([W.h(0)], x, scratch=x)
+    assert torch.equal(x, before)
+
+
+def test_norm_preserved_every_gate_n20():
+    n = 20
+    gates = W.random_layered(n, 1, 20) + W.qft(n)[:30]
+    psi = to_dev(W.random_state(n, 20))
+    arr = D.gate_array(gates)
+    for g in range(len(gates)):
+        D.apply_circuit(gates, psi, begin=g, end=g + 1, marshalled=arr)
+        nrm = torch.linalg.vector_norm(psi).item()
+        assert abs(nrm - 1) <= 1e-12, g
+
+
+# --------------------------------------------------------------------------
+# Adjoint gradients
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,layers", [(4, 2), (8, 3), (12, 2)])
+def test_adjoint_matches_parameter_shift(n, layers):
+    gates, theta, terms = W.hea(n, layers, 11 + n)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = W.zero_state(n)
+    e, g = D.adjoint_grad(gates, H, to_dev(psi0), len(theta))
+    e_ref = orc.energy(psi0, n, gates, terms)
+    assert abs(e - e_ref) <= 1e-12
+    ps = orc.param_shift_grad(psi0, n, gates, terms, len(theta))
+    assert np.linalg.norm(g - ps) <= 1e-10 * max(1.0, np.linalg.norm(ps))
+    fd = orc.fd_grad(psi0, n, gates, terms, len(theta), h=1e-3)
+    assert np.linalg.norm(g - fd) / np.linalg.norm(fd) <= 1e-6
+
+
+def test_adjoint_all_rotation_kinds():
+    rng = np.random.default_rng(77)
+    n = 6
+    gates = []
+    pidx = 0
+    for kind, nt in [("RX", 1), ("RY", 1), ("RZ", 1), ("P", 1), ("RXX", 2), ("RYY", 2), ("RZZ", 2)]:
+        qs = [int(q) for q in rng.permutation(n)[:nt]]
+        gates.append(W.u3(*rng.uniform(0, 6, 3), int(rng.integers(n))))
+        gates.append(W.Gate(kind, tuple(qs), (), (float(rng.uniform(0, 6)),), pidx, float(rng.uniform(0.5, 2))))
+        pidx += 1
+    gates.append(W.Gate("P", (1,), (4,), (0.8,), pidx, 1.0))  # controlled phase
+    pidx += 1
+    gates.append(W.Gate("RY", (2,), (0,), (1.1,), pidx, 1.0))  # controlled rotation
+    pidx += 1
+    terms = [(int(rng.integers(0, 64)), int(rng.integers(0, 64)), float(rng.standard_normal())) for _ in range(6)]
+    H = D.from_pauli_sum(n, terms)
+    psi0 = W.random_state(n, 5)
+    e, g = D.adjoint_grad(gates, H, to_dev(psi0), pidx)
+    assert abs(e - orc.energy(psi0, n, gates, terms)) <= 1e-12
+    fd = orc.fd_grad(psi0, n, gates, terms, pidx, h=1e-4)
+    assert np.max(np.abs(g - fd)) <= 1e-7 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_adjoint_hea20_sampled_fd():
+    """HEA n=20 (8 layers, 320 parameters, CZ rings): energy against the
+    oracle and sampled gradient entries against central differences."""
+    n, layers = 20, 8
+    gates, theta, terms = W.hea(n, layers, 20)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = W.zero_state(n)
+    e, g = D.adjoint_grad(gates, H, to_dev(psi0), len(theta))
+    assert abs(e - orc.energy(psi0, n, gates, terms)) <= 1e-11
+    h = 1e-4
+    for j in [0, 137, 319]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += h
+        tm[j] -= h
+        fd = (orc.energy(psi0, n, W.hea_gates(n, layers, tp), terms)
+              - orc.energy(psi0, n, W.hea_gates(n, layers, tm), terms)) / (2 * h)
+        assert abs(g[j] - fd) <= 1e-6 * max(1.0, abs(fd)), j
+
+
+def test_autograd_function():
+    n, layers = 6, 2
+    gates, theta, terms = W.hea(n, layers, 4)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = to_dev(W.zero_state(n))
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    E = D.DiaqExpectation.apply(th, lambda t: W.hea_gates(n, layers, t), H, psi0)
+    E.backward()
+    ps = orc.param_shift_grad(W.zero_state(n), n, gates, terms, len(theta))
+    assert np.allclose(th.grad.numpy(), ps, atol=1e-10, rtol=0)
