@@ -1,0 +1,264 @@
+"""Benchmark of the DiaQ hot path on one MI355X.
+
+Workload (one "step"): the random layered circuit on n = 28 qubits -- 20
+layers of U3 on every qubit plus alternating CX brickwork, 830 gates, seed
+28, complex128 -- applied to a resident state vector, every gate expanded
+to its DiaQ diagonals and applied by the DiaQ SpMV; then the Ising energy
+<psi| sum_i a_i Z_i Z_{i+1} |psi> of the result (one diagonal).
+
+Prints one JSON line.  ``value`` is the whole step's effective HBM rate:
+algorithmic bytes (expansion writes E elements, each product reads E
+elements plus x and writes y) divided by wall time of the timed steps.
+``roofline`` describes the dominant kernel, the DiaQ SpMV, from HIP events
+recorded around each of its launches inside the timed region.
+``cpu_baseline`` times the CPU oracle on a bounded sample of the same
+circuit on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor peak
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--layers", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=28)
+    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="time budget of the CPU-oracle sample (0 disables it)")
+    ap.add_argument("--extras", type=int, default=1, help="also time adjoint vs parameter shift (HEA n=20)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
+                    help="copy: run a plain device copy of 2^n complex elements (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_mode(a):
+    """A plain copy kernel of known size: reads and writes 2^n elements."""
+    import torch
+    N = 1 << a.n
+    tdt = torch.complex128 if a.dtype == "c128" else torch.complex64
+    x = torch.ones(N, dtype=tdt, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    nb = x.numel() * x.element_size()
+    print(json.dumps({"mode": "copy", "bytes_read": nb, "bytes_written": nb, "copies": a.steps,
+                      "GBps": round(2 * nb / dt / 1e9, 1)}), flush=True)
+
+
+def _traffic_from_profiles(kernel_src: str):
+    """HBM traffic per SpMV launch measured with rocprofv3 counters, if the
+    committed summary was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "spmv_hbm_traffic_n28.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    want = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    if kv.get("spmv_source_sha256_16") != want:
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(n, gates, budget_s, bytes_of_gate):
+    """The CPU oracle, as it stands, on the first gates of the same circuit
+    until the time budget is spent."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2405_01250_amd import inputs as W
+
+    orc.build()
+    psi = W.zero_state(n)
+    done, nbytes = 0, 0.0
+    t0 = time.perf_counter()
+    for g in gates:
+        orc.apply_gate(psi, n, g)
+        done += 1
+        nbytes += bytes_of_gate(g)
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    del psi, np
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "gates_per_s": done / dt,
+            "sample": "first %d of %d gates of the n=%d random layered circuit, complex128, in-place "
+                      "bit-manipulation oracle (C, OpenMP); GB/s uses the same algorithmic byte model "
+                      "as value" % (done, len(gates), n)}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if a.mode == "copy":
+        copy_mode(a)
+        return
+    import numpy as np
+    import torch
+
+    from paper_2405_01250_amd import diaq as D
+    from paper_2405_01250_amd import inputs as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    n = a.n
+    N = 1 << n
+    s = 16 if a.dtype == "c128" else 8
+    tdt = torch.complex128 if a.dtype == "c128" else torch.complex64
+    gates = W.random_layered(n, a.layers, a.seed)
+    arr = D.gate_array(gates)
+
+    def e_of(g):
+        offs, nv = D.from_gate_query(g, n)
+        return nv
+
+    E = [e_of(g) for g in gates]
+    step_bytes = sum(s * e + s * (e + 2 * N) for e in E)  # expansion + product
+    spmv_bytes = sum(s * (e + 2 * N) for e in E)
+
+    # observable: Ising energy sum a_i Z_i Z_{i+1} (one diagonal)
+    rng = np.random.default_rng(a.seed)
+    coef = rng.standard_normal(n - 1)
+    terms = [(0, (1 << i) | (1 << (i + 1)), float(coef[i])) for i in range(n - 1)]
+    Hzz = D.from_pauli_sum(n, terms, dtype=tdt)
+
+    state = torch.zeros(N, dtype=tdt, device=dev)
+    state[0] = 1
+    scratch = torch.empty_like(state)
+    ctx = D.context()
+
+    def step():
+        D.apply_circuit(gates, state, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
+        return D.expect(Hzz, state)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    D.profile_start(ctx)
+    t0 = time.perf_counter()
+    energies = []
+    for _ in range(a.steps):
+        energies.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = D.profile_stop(ctx)
+    dt = t1 - t0
+    ms_per_step = dt / a.steps * 1e3
+    norm = float(torch.linalg.vector_norm(state).item())
+
+    spmv_avg_ms = prof["spmv_ms"] / max(1, prof["spmv_launches"])
+    spmv_bytes_per_launch = prof["spmv_bytes"] / max(1, prof["spmv_launches"])
+    achieved = spmv_bytes_per_launch / (spmv_avg_ms * 1e-3) / 1e9
+    traffic = _traffic_from_profiles(os.path.join(ROOT, "paper_2405_01250_amd", "csrc", "spmv.hip"))
+
+    out = {
+        "metric": "DiaQ SpMV effective HBM GB/s + gates/s at n=28; adjoint grads/s vs plain",
+        "value": round(step_bytes * a.steps / dt / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.dtype,
+        "data": "synthetic",
+        "config": {"workload": "random layered circuit n=%d, %d layers (U3 on every qubit + CX brickwork), "
+                               "%d gates, seed %d, |0..0>, plain per-gate expansion + DiaQ SpMV, then "
+                               "<Z_iZ_i+1> energy" % (n, a.layers, len(gates), a.seed),
+                   "n": n, "gates": len(gates), "layers": a.layers},
+        "gates_per_s": round(len(gates) * a.steps / dt, 2),
+        "spmv_GBps": round(achieved, 1),
+        "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)
+        if prof["expand_ms"] else None,
+        "spmv_share_of_step": round(prof["spmv_ms"] / (dt * 1e3), 3),
+        "check": {"final_norm": norm, "energy": energies[-1].real},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": "spmv_kernel (DiaQ SpMV, Alg. 2)",
+                     "bytes_per_launch": spmv_bytes_per_launch, "avg_launch_ms": round(spmv_avg_ms, 4),
+                     "launches": prof["spmv_launches"]},
+    }
+    if abs(norm - 1) > 1e-9:
+        out["check"]["error"] = "norm drifted"
+
+    if a.extras:
+        out["adjoint"] = adjoint_extra(D, W, torch, dev)
+    if a.cpu_seconds > 0:
+        del state, scratch, Hzz
+        torch.cuda.empty_cache()
+        eb = {id(g): s * e + s * (e + 2 * N) for g, e in zip(gates, E)}
+        out["cpu_baseline"] = cpu_baseline(n, gates, a.cpu_seconds, lambda g: eb[id(g)])
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_extra(D, W, torch, dev):
+    """Adjoint gradient of the HEA (n=20, 8 layers, 320 parameters) against
+    the plain per-gate path: one adjoint sweep vs the 2 * 320 forward passes
+    the parameter-shift rule needs (timed forward pass x 640)."""
+    n, layers = 20, 8
+    gates, theta, terms = W.hea(n, layers, 20)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = torch.zeros(1 << n, dtype=torch.complex128, device=dev)
+    psi0[0] = 1
+    work = torch.empty(3 << n, dtype=torch.complex128, device=dev)
+    D.adjoint_grad(gates, H, psi0, len(theta), work=work)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e, g = D.adjoint_grad(gates, H, psi0, len(theta), work=work)
+    t_adj = (time.perf_counter() - t0) / reps
+    psi = psi0.clone()
+    scratch = torch.empty_like(psi)
+    arr = D.gate_array(gates)
+    D.apply_circuit(gates, psi, scratch=scratch, marshalled=arr)
+    D.expect(H, psi)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        psi.copy_(psi0)
+        D.apply_circuit(gates, psi, scratch=scratch, marshalled=arr)
+        D.expect(H, psi)
+    t_fwd = (time.perf_counter() - t0) / reps
+    return {"workload": "HEA n=20, 8 layers (RY, RZ, CZ ring), 320 params, H = sum a ZZ + sum b X",
+            "adjoint_grads_per_s": round(1 / t_adj, 3), "adjoint_ms": round(t_adj * 1e3, 2),
+            "forward_ms": round(t_fwd * 1e3, 2),
+            "param_shift_grads_per_s": round(1 / (2 * len(theta) * t_fwd), 4),
+            "speedup_vs_param_shift": round(2 * len(theta) * t_fwd / t_adj, 1),
+            "energy": e}
+
+
+if __name__ == "__main__":
+    main()

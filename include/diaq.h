@@ -282,6 +282,29 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                 int64_t nparams, double* expval,
                                 double* grad);
 
+/* ------------------------------------------------------------------ */
+/* Kernel timing (the counterpart of the simulator trace timer the paper
+ * reads its times from, Sec. VII)                                      */
+/* ------------------------------------------------------------------ */
+
+/* Totals over the launches issued by diaq_apply_circuit between start and
+ * stop, timed with HIP events recorded on the context's stream around each
+ * kernel.  Bytes are algorithmic: an expansion writes E stored elements; a
+ * product reads E stored elements and one vector and writes one vector
+ * (E + 2N elements), whatever the caches do. */
+typedef struct diaq_profile {
+  int64_t expand_launches;
+  double expand_ms;
+  double expand_bytes;
+  int64_t spmv_launches;
+  double spmv_ms;
+  double spmv_bytes;
+} diaq_profile_t;
+
+diaq_status_t diaq_profile_start(diaq_ctx_t ctx);
+/* Synchronises the stream, fills *out, and stops recording. */
+diaq_status_t diaq_profile_stop(diaq_ctx_t ctx, diaq_profile_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,30 @@ diaq_status_t new_dia(diaq_ctx* ctx, int n, diaq_dtype_t dt, const std::vector<i
   return DIAQ_OK;
 }
 
+size_t prof_mark(diaq_ctx* ctx) {
+  if (!ctx->profiling) return SIZE_MAX;
+  if (ctx->events_used == ctx->events.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return SIZE_MAX;
+    }
+    ctx->events.push_back(e);
+  }
+  const size_t i = ctx->events_used;
+  if (hipEventRecord(ctx->events[i], ctx->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return SIZE_MAX;
+  }
+  ctx->events_used++;
+  return i;
+}
+
+void prof_interval(diaq_ctx* ctx, size_t ev0, size_t ev1, int kind, double bytes) {
+  if (!ctx->profiling || ev0 == SIZE_MAX || ev1 == SIZE_MAX) return;
+  ctx->intervals.push_back({ev0, ev1, kind, bytes});
+}
+
 SpmvOp op_of(const diaq_dia* A, bool transpose, bool conjugate) {
   SpmvOp op;
   op.n = A->nqubits;
@@ -193,9 +217,41 @@ diaq_status_t diaq_synchronize(diaq_ctx_t ctx) {
   return DIAQ_OK;
 }
 
+diaq_status_t diaq_profile_start(diaq_ctx_t ctx) {
+  if (!ctx) return fail(DIAQ_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  ctx->profiling = true;
+  ctx->events_used = 0;
+  ctx->intervals.clear();
+  return DIAQ_OK;
+}
+
+diaq_status_t diaq_profile_stop(diaq_ctx_t ctx, diaq_profile_t* out) {
+  if (!ctx || !out) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  DIAQ_HIP(hipStreamSynchronize(ctx->stream));
+  for (const auto& iv : ctx->intervals) {
+    float ms = 0;
+    DIAQ_HIP(hipEventElapsedTime(&ms, ctx->events[iv.ev0], ctx->events[iv.ev1]));
+    if (iv.kind == 0) {
+      out->expand_launches++;
+      out->expand_ms += ms;
+      out->expand_bytes += iv.bytes;
+    } else {
+      out->spmv_launches++;
+      out->spmv_ms += ms;
+      out->spmv_bytes += iv.bytes;
+    }
+  }
+  ctx->profiling = false;
+  ctx->events_used = 0;
+  ctx->intervals.clear();
+  return DIAQ_OK;
+}
+
 diaq_status_t diaq_destroy(diaq_ctx_t ctx) {
   if (!ctx) return DIAQ_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   for (Workspace* w : {&ctx->diag, &ctx->red, &ctx->aux})
     if (w->ptr) (void)hipFree(w->ptr);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);

@@ -38,7 +38,18 @@ diaq_status_t prepare_gates(const diaq_gate_t* gates, int64_t ngates, int n, Pre
 diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t>& offs, int n, diaq_dtype_t dt,
                    bool adjoint, void** x, void** y) {
   const std::vector<int64_t> st = packing_starts(offs, n);
+  const double s = double(elem_bytes(dt));
+  const double E = double(st.back()), N = double(int64_t(1) << n);
+  const size_t e0 = prof_mark(ctx);
   DIAQ_TRY(launch_expand(ctx, lg, n, dt, offs, st, ctx->diag.ptr));
+  const size_t e1 = prof_mark(ctx);
+  prof_interval(ctx, e0, e1, 0, s * E);
+  struct Close {
+    diaq_ctx* c;
+    size_t e1;
+    double bytes;
+    ~Close() { prof_interval(c, e1, prof_mark(c), 1, bytes); }
+  } close_spmv{ctx, e1, s * (E + 2 * N)};
   SpmvOp op;
   op.n = n;
   op.dtype = dt;

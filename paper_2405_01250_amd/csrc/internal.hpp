@@ -69,6 +69,16 @@ struct diaq_ctx {
   // SpMV tuning (0 = defaults)
   int spmv_block = 0;
   int spmv_rows = 0;
+  // kernel timing: events recorded around expansion and product launches
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
+  size_t events_used = 0;
+  struct Interval {
+    size_t ev0, ev1;
+    int kind;        // 0 = expansion, 1 = product
+    double bytes;
+  };
+  std::vector<Interval> intervals;
 };
 
 struct diaq_dia {
@@ -181,5 +191,10 @@ diaq_status_t new_dia(diaq_ctx* ctx, int n, diaq_dtype_t dt,
 
 // SpMV operand view of a DiaQ matrix with the given effective flags.
 SpmvOp op_of(const diaq_dia* A, bool transpose, bool conjugate);
+
+// Kernel timing: record an event on the context stream (returns its index
+// in ctx->events, or SIZE_MAX when profiling is off) and close an interval.
+size_t prof_mark(diaq_ctx* ctx);
+void prof_interval(diaq_ctx* ctx, size_t ev0, size_t ev1, int kind, double bytes);
 
 }  // namespace diaq

@@ -52,6 +52,12 @@ class diaq_plan_t(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 3)]
 
 
+class diaq_profile_t(ctypes.Structure):
+    _fields_ = [("expand_launches", ctypes.c_int64), ("expand_ms", ctypes.c_double),
+                ("expand_bytes", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
+                ("spmv_ms", ctypes.c_double), ("spmv_bytes", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -85,6 +91,8 @@ _SIGS = {
     "diaq_expect": [_P, _P, _P, _P, ctypes.POINTER(_D)],
     "diaq_adjoint_grad": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _P, _P, _P, _I64,
                           ctypes.POINTER(_D), ctypes.POINTER(_D)],
+    "diaq_profile_start": [_P],
+    "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
 
 EXPORTED = sorted(_SIGS) + ["diaq_last_error", "diaq_status_string"]
@@ -422,6 +430,21 @@ def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: in
                                     _P(work.data_ptr()), nparams, ctypes.byref(e),
                                     grad.ctypes.data_as(ctypes.POINTER(_D))))
     return e.value, grad[:nparams]
+
+
+def profile_start(ctx: Context | None = None):
+    """Start timing apply_circuit's kernels with HIP events."""
+    ctx = ctx or context()
+    _check(load().diaq_profile_start(ctx.handle))
+
+
+def profile_stop(ctx: Context | None = None) -> dict:
+    """Stop timing; returns launch counts, milliseconds and algorithmic
+    bytes of the expansion and product kernels (synchronises)."""
+    ctx = ctx or context()
+    p = diaq_profile_t()
+    _check(load().diaq_profile_stop(ctx.handle, ctypes.byref(p)))
+    return {f: getattr(p, f) for f, _ in diaq_profile_t._fields_}
 
 
 class DiaqExpectation(torch.autograd.Function):
