@@ -283,6 +283,32 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                 double* grad);
 
 /* ------------------------------------------------------------------ */
+/* Tuning knobs of the product kernel (set by the autotuner)            */
+/* ------------------------------------------------------------------ */
+
+/* Zero in any field selects the built-in default. */
+typedef struct diaq_tuning {
+  int32_t spmv_rows;       /* rows per lane in one tile: 1, 2 or 4 */
+  int32_t spmv_group_bits; /* how many high coupling qubits a workgroup
+                              pairs its tiles over: 1..3, or -1 for none */
+  int32_t spmv_chunk;      /* diagonals whose loads are issued together:
+                              1 or 3 */
+  int32_t spmv_nontemporal;/* 1: stream diagonal values and y with
+                              non-temporal hints; -1: plain accesses */
+  int32_t spmv_group_min_qubit; /* only qubits >= this are paired (their
+                              partner rows are too far apart in launch
+                              order to meet in the caches) */
+  int32_t expand_nontemporal; /* 1: write expanded diagonals with
+                              non-temporal hints; -1: plain stores */
+  int32_t diag_pad;        /* elements of padding between the expanded
+                              diagonals in the circuit workspace (-1: none) */
+  int32_t reserved[1];
+} diaq_tuning_t;
+
+diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);
+diaq_status_t diaq_get_tuning(diaq_ctx_t ctx, diaq_tuning_t* t);
+
+/* ------------------------------------------------------------------ */
 /* Kernel timing (the counterpart of the simulator trace timer the paper
  * reads its times from, Sec. VII)                                      */
 /* ------------------------------------------------------------------ */

@@ -217,6 +217,28 @@ diaq_status_t diaq_synchronize(diaq_ctx_t ctx) {
   return DIAQ_OK;
 }
 
+diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t) {
+  if (!ctx || !t) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (t->spmv_rows != 0 && t->spmv_rows != 1 && t->spmv_rows != 2 && t->spmv_rows != 4)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_rows must be 0, 1, 2 or 4");
+  if (t->spmv_group_bits < -1 || t->spmv_group_bits > 3)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_group_bits must be in [-1, 3]");
+  if (t->spmv_chunk != 0 && t->spmv_chunk != 1 && t->spmv_chunk != 3)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_chunk must be 0, 1 or 3");
+  if (t->diag_pad < -1 || t->diag_pad > (1 << 24))
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "diag_pad must be in [-1, 2^24]");
+  if (t->spmv_group_min_qubit < 0 || t->spmv_group_min_qubit > 63)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_group_min_qubit must be in [0, 63]");
+  ctx->tuning = *t;
+  return DIAQ_OK;
+}
+
+diaq_status_t diaq_get_tuning(diaq_ctx_t ctx, diaq_tuning_t* t) {
+  if (!ctx || !t) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+  *t = ctx->tuning;
+  return DIAQ_OK;
+}
+
 diaq_status_t diaq_profile_start(diaq_ctx_t ctx) {
   if (!ctx) return fail(DIAQ_ERR_INVALID_ARGUMENT, "ctx is NULL");
   ctx->profiling = true;

@@ -35,11 +35,21 @@ diaq_status_t prepare_gates(const diaq_gate_t* gates, int64_t ngates, int n, Pre
 
 // Expand gate g into the workspace and apply it (or its adjoint) from *x
 // into *y; swaps the pointers unless the gate ran in place.
+// Packing starts in the circuit workspace: the compact diagonals one after
+// another, optionally separated by ctx->tuning.diag_pad elements so that the
+// streams of one product do not sit at power-of-two distances.
+std::vector<int64_t> workspace_starts(const diaq_ctx* ctx, const std::vector<int64_t>& offs, int n) {
+  std::vector<int64_t> st = packing_starts(offs, n);
+  const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
+  for (size_t k = 1; k < st.size(); k++) st[k] += int64_t(k) * pad;
+  return st;
+}
+
 diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t>& offs, int n, diaq_dtype_t dt,
                    bool adjoint, void** x, void** y) {
-  const std::vector<int64_t> st = packing_starts(offs, n);
+  const std::vector<int64_t> st = workspace_starts(ctx, offs, n);
   const double s = double(elem_bytes(dt));
-  const double E = double(st.back()), N = double(int64_t(1) << n);
+  const double E = double(packing_starts(offs, n).back()), N = double(int64_t(1) << n);
   const size_t e0 = prof_mark(ctx);
   DIAQ_TRY(launch_expand(ctx, lg, n, dt, offs, st, ctx->diag.ptr));
   const size_t e1 = prof_mark(ctx);
@@ -85,7 +95,8 @@ diaq_status_t check_vectors(int n, diaq_dtype_t dt, const void* a, const void* b
 // the final state (state or scratch).
 diaq_status_t run_plain(diaq_ctx* ctx, const Prepared& p, int64_t begin, int64_t end, int n, diaq_dtype_t dt,
                         void* state, void* scratch, void** result) {
-  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(p.max_values) * elem_bytes(dt)));
+  const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
+  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(p.max_values + (kMaxArgDiags + 1) * pad) * elem_bytes(dt)));
   void* x = state;
   void* y = scratch;
   for (int64_t g = begin; g < end; g++) DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], n, dt, false, &x, &y));

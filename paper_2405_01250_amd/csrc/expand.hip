@@ -38,7 +38,18 @@ struct ExpandArgs {
   double m[8][8][2];
 };
 
-template <typename R>
+template <bool NT, typename V>
+__device__ __forceinline__ void put(V* p, const V& v) {
+  if constexpr (NT) {
+    using N2 = typename HIP_vector_base<decltype(V{}.x), 2>::Native_vec_;
+    N2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<N2*>(p));
+  } else {
+    *p = v;
+  }
+}
+
+template <typename R, bool NT>
 __global__ __launch_bounds__(kBlock) void expand_kernel(ExpandArgs a, typename Vec<R>::V* __restrict__ out) {
   using V = typename Vec<R>::V;
   __shared__ double sm[64][2];
@@ -74,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(ExpandArgs a, typename V
         vi = sm[r * dim + c][1];
       }
     }
-    dst[t] = V{R(vr), R(vi)};
+    put<NT>(dst + t, V{R(vr), R(vi)});
   }
 }
 
@@ -144,10 +155,22 @@ diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n, diaq_dtyp
   std::memcpy(a.m, lg.m, sizeof(a.m));
   const int64_t gx = (maxlen + kBlock * kPerThread - 1) / (kBlock * kPerThread);
   dim3 grid(unsigned(gx), unsigned(offs.size()));
-  if (dt == DIAQ_C128)
-    hipLaunchKernelGGL(expand_kernel<double>, grid, dim3(kBlock), 0, ctx->stream, a, static_cast<double2*>(values));
-  else
-    hipLaunchKernelGGL(expand_kernel<float>, grid, dim3(kBlock), 0, ctx->stream, a, static_cast<float2*>(values));
+  const bool nt = ctx->tuning.expand_nontemporal > 0;
+  if (dt == DIAQ_C128) {
+    if (nt)
+      hipLaunchKernelGGL((expand_kernel<double, true>), grid, dim3(kBlock), 0, ctx->stream, a,
+                         static_cast<double2*>(values));
+    else
+      hipLaunchKernelGGL((expand_kernel<double, false>), grid, dim3(kBlock), 0, ctx->stream, a,
+                         static_cast<double2*>(values));
+  } else {
+    if (nt)
+      hipLaunchKernelGGL((expand_kernel<float, true>), grid, dim3(kBlock), 0, ctx->stream, a,
+                         static_cast<float2*>(values));
+    else
+      hipLaunchKernelGGL((expand_kernel<float, false>), grid, dim3(kBlock), 0, ctx->stream, a,
+                         static_cast<float2*>(values));
+  }
   DIAQ_HIP(hipGetLastError());
   return DIAQ_OK;
 }

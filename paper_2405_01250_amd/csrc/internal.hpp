@@ -67,8 +67,8 @@ struct diaq_ctx {
   double* pinned = nullptr; // host-pinned landing zone for results
   size_t pinned_bytes = 0;
   // SpMV tuning (0 = defaults)
-  int spmv_block = 0;
-  int spmv_rows = 0;
+  diaq_tuning_t tuning{};
+  int spmv_rows = 0;  // per-call override from a plan
   // kernel timing: events recorded around expansion and product launches
   bool profiling = false;
   std::vector<hipEvent_t> events;

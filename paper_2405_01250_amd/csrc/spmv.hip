@@ -70,11 +70,14 @@ struct DiagSrc {
 };
 
 // (applied offset e, value base vb): row i uses vals[vb + i] * x[i + e].
+// DM selects the device table (matrices with many diagonals) over the
+// kernel-argument copy; both are uniform, scalar-loaded reads.
+template <bool DM>
 __device__ __forceinline__ void diag_at(const DiagArgs& da, const DiagSrc& src, int k,
                                         int64_t& e, int64_t& vb) {
   const int kk = src.transpose ? (src.nd - 1 - k) : k;
   int64_t d, st;
-  if (src.dmeta) {
+  if constexpr (DM) {
     d = src.dmeta[kk];
     st = src.dmeta[src.nd + kk];
   } else {
@@ -106,15 +109,43 @@ __device__ __forceinline__ void cfma(typename Vec<R>::V& acc, const typename Vec
   acc.y = fma(a.y, b.x, acc.y);
 }
 
+template <typename V>
+using NativeOf = typename HIP_vector_base<decltype(V{}.x), 2>::Native_vec_;
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V* p) {
+  if constexpr (NT) {
+    const auto t = __builtin_nontemporal_load(reinterpret_cast<const NativeOf<V>*>(p));
+    return V{t[0], t[1]};
+  } else {
+    return *p;
+  }
+}
+
+template <bool NT, typename V>
+__device__ __forceinline__ void st(V* p, const V& v) {
+  if constexpr (NT) {
+    NativeOf<V> t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<NativeOf<V>*>(p));
+  } else {
+    *p = v;
+  }
+}
+
 // Computes acc[s*RPT + j] = (op(A) x)[row(s, j)] for the G*RPT rows a lane
 // owns; rows outside [0, N) (only when N < tile) are left at zero.
-template <typename R, int RPT, int G, bool CHECK>
+// Diagonals are taken KC at a time: all their values are loaded, then all
+// the x loads they need are issued, then the multiplies run, so the x
+// elements that paired rows share are requested back to back.  NT marks
+// the single-use value stream non-temporal.
+template <typename R, int RPT, int G, bool CHECK, int KC, bool NT, bool DM>
 __device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src, const RowMap& m,
                                          const typename Vec<R>::V* __restrict__ vals,
                                          const typename Vec<R>::V* __restrict__ x, int64_t base,
                                          typename Vec<R>::V (&acc)[G * RPT],
                                          int64_t (&row)[G * RPT]) {
   using V = typename Vec<R>::V;
+  constexpr int ROWS = G * RPT;
   const int64_t N = m.N;
 #pragma unroll
   for (int s = 0; s < G; s++)
@@ -123,36 +154,52 @@ __device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src,
       row[s * RPT + j] = base + group_offset(s, m) + j * kBlock + threadIdx.x;
       acc[s * RPT + j] = V{0, 0};
     }
-  for (int k = 0; k < src.nd; k++) {
-    int64_t e, vb;
-    diag_at(da, src, k, e, vb);
-    const int64_t lo = e < 0 ? -e : 0;
-    const int64_t hi = e > 0 ? N - e : N;
-    V v[G * RPT];
+  for (int k0 = 0; k0 < src.nd; k0 += KC) {
+    // the chunk's diagonal descriptors first, so no value load waits on them
+    int64_t ek[KC], vbk[KC], lok[KC], hik[KC];
 #pragma unroll
-    for (int r = 0; r < G * RPT; r++) {
-      const int64_t i = row[r];
-      const bool in = (i >= lo) && (i < hi) && (!CHECK || i < N);
-      v[r] = in ? vals[vb + i] : V{0, 0};
+    for (int c = 0; c < KC; c++) {
+      int64_t e = 0, vb = 0;
+      if ((k0 + c) < src.nd) diag_at<DM>(da, src, k0 + c, e, vb);
+      ek[c] = e;
+      vbk[c] = vb;
+      lok[c] = (k0 + c) < src.nd ? (e < 0 ? -e : 0) : N;
+      hik[c] = e > 0 ? N - e : N;
+    }
+    V v[KC][ROWS];
+#pragma unroll
+    for (int c = 0; c < KC; c++) {
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        const int64_t i = row[r];
+        const bool in = (i >= lok[c]) && (i < hik[c]) && (!CHECK || i < N);
+        v[c][r] = in ? ld<NT>(vals + vbk[c] + i) : V{0, 0};
+      }
     }
     if (src.conjugate) {
 #pragma unroll
-      for (int r = 0; r < G * RPT; r++) v[r].y = -v[r].y;
-    }
-    // issue every x load of this diagonal before the first multiply, so the
-    // loads of all owned rows are in flight together
-    V xv[G * RPT];
+      for (int c = 0; c < KC; c++)
 #pragma unroll
-    for (int r = 0; r < G * RPT; r++) {
-      xv[r] = V{0, 0};
-      if (nonzero(v[r])) xv[r] = x[row[r] + e];
+        for (int r = 0; r < ROWS; r++) v[c][r].y = -v[c][r].y;
     }
+    // issue every x load of the chunk before the first multiply
+    V xv[KC][ROWS];
 #pragma unroll
-    for (int r = 0; r < G * RPT; r++) cfma<R>(acc[r], v[r], xv[r]);
+    for (int c = 0; c < KC; c++)
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        xv[c][r] = V{0, 0};
+        if (nonzero(v[c][r])) xv[c][r] = x[row[r] + ek[c]];
+      }
+    // ascending diagonal order within every row
+#pragma unroll
+    for (int c = 0; c < KC; c++)
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) cfma<R>(acc[r], v[c][r], xv[c][r]);
   }
 }
 
-template <typename R, int RPT, int G, bool CHECK>
+template <typename R, int RPT, int G, bool CHECK, int KC, bool NT, bool DM>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(DiagArgs da, DiagSrc src, RowMap m,
                                                       const typename Vec<R>::V* __restrict__ vals,
                                                       const typename Vec<R>::V* __restrict__ x,
@@ -161,10 +208,10 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(DiagArgs da, DiagSrc src, 
   const int64_t base = insert_zero_bits(int64_t(blockIdx.x) << m.tile_log2, m);
   V acc[G * RPT];
   int64_t row[G * RPT];
-  dia_rows<R, RPT, G, CHECK>(da, src, m, vals, x, base, acc, row);
+  dia_rows<R, RPT, G, CHECK, KC, NT, DM>(da, src, m, vals, x, base, acc, row);
 #pragma unroll
   for (int r = 0; r < G * RPT; r++)
-    if (!CHECK || row[r] < m.N) y[row[r]] = acc[r];
+    if (!CHECK || row[r] < m.N) st<NT>(y + row[r], acc[r]);
 }
 
 // In-place variant for matrices whose only diagonal is the principal one.
@@ -209,7 +256,7 @@ __device__ __forceinline__ void block_reduce_store(double re, double im, double2
   }
 }
 
-template <typename R, int RPT, int G, bool CHECK>
+template <typename R, int RPT, int G, bool CHECK, int KC, bool NT, bool DM>
 __global__ __launch_bounds__(kBlock) void expect_kernel(DiagArgs da, DiagSrc src, RowMap m,
                                                         const typename Vec<R>::V* __restrict__ vals,
                                                         const typename Vec<R>::V* __restrict__ psi,
@@ -219,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void expect_kernel(DiagArgs da, DiagSrc src
   const int64_t base = insert_zero_bits(int64_t(blockIdx.x) << m.tile_log2, m);
   V acc[G * RPT];
   int64_t row[G * RPT];
-  dia_rows<R, RPT, G, CHECK>(da, src, m, vals, phi, base, acc, row);
+  dia_rows<R, RPT, G, CHECK, KC, NT, DM>(da, src, m, vals, phi, base, acc, row);
   double re = 0, im = 0;
 #pragma unroll
   for (int r = 0; r < G * RPT; r++) {
@@ -322,16 +369,34 @@ struct Plan {
   RowMap map;
   int rpt;
   int g;
+  int kc;
+  bool nt;
   bool check;
   int64_t blocks;
 };
 
-Plan plan_rows(const SpmvOp& op, int rpt_hint) {
+// Row tiling and kernel variant.  Defaults (measured on MI355X at n = 28,
+// one-qubit gates on every qubit): 1 row per lane per tile, tiles paired
+// over up to 3 coupling qubits >= 21 (partners closer than that meet in the
+// 256 MB last-level cache anyway), one diagonal's loads at a time, and
+// non-temporal value / y streams so they do not evict x.
+constexpr int kDefaultRows = 1;
+constexpr int kDefaultGroupMinQubit = 21;
+
+Plan plan_rows(const SpmvOp& op, const diaq_tuning_t& t, int rpt_override) {
   Plan p{};
   const int n = op.n;
   p.map.N = int64_t(1) << n;
-  int rpt = rpt_hint > 0 ? rpt_hint : 2;
-  if (rpt != 1 && rpt != 2 && rpt != 4) rpt = 2;
+  int rpt = rpt_override > 0 ? rpt_override : (t.spmv_rows > 0 ? t.spmv_rows : kDefaultRows);
+  if (rpt != 1 && rpt != 2 && rpt != 4) rpt = kDefaultRows;
+  int max_bits = t.spmv_group_bits < 0 ? 0 : (t.spmv_group_bits == 0 ? 3 : std::min(3, t.spmv_group_bits));
+  if (op.nd > kMaxArgDiags) {
+    // descriptor-table kernels come in one shape: 2 rows per lane, no grouping
+    rpt = 2;
+    max_bits = 0;
+  }
+  p.kc = (t.spmv_chunk == 3) ? 3 : 1;
+  p.nt = t.spmv_nontemporal >= 0;
   int tile_log2 = 8 + (rpt == 4 ? 2 : rpt == 2 ? 1 : 0);
   if (n < tile_log2) {
     // tiny matrix: one row per lane, bounds-checked
@@ -345,13 +410,16 @@ Plan plan_rows(const SpmvOp& op, int rpt_hint) {
   }
   // group the highest coupling bits at or above the tile size
   int bits[64], nb = 0;
-  for (int q = n - 1; q >= tile_log2 && nb < 3; q--)
+  const int qmin =
+      std::max(tile_log2, t.spmv_group_min_qubit > 0 ? t.spmv_group_min_qubit : kDefaultGroupMinQubit);
+  for (int q = n - 1; q >= qmin && nb < max_bits; q--)
     if ((op.qubit_mask >> q) & 1) bits[nb++] = q;
-  // G = 8 with 2 rows per lane is 16 live accumulators; drop to 1 row.
-  if (nb == 3 && rpt > 1) {
-    rpt = 1;
-    tile_log2 = 8;
+  // at most 4 rows per lane: larger groups take fewer rows per tile
+  while ((rpt << nb) > 4 && rpt > 1) {
+    rpt >>= 1;
+    tile_log2--;
   }
+  if ((rpt << nb) > 4) p.kc = 1;  // G = 8: keep the register budget
   p.rpt = rpt;
   p.map.tile_log2 = tile_log2;
   p.map.ng = nb;
@@ -362,6 +430,31 @@ Plan plan_rows(const SpmvOp& op, int rpt_hint) {
   return p;
 }
 
+template <typename R, int RPT, int G, bool CHK, int KC, bool NT, bool DM>
+void launch_one(diaq_ctx* ctx, const DiagArgs& da, const DiagSrc& src, const Plan& p,
+                const typename Vec<R>::V* v, const typename Vec<R>::V* x, typename Vec<R>::V* y,
+                double2* partial, const typename Vec<R>::V* psi) {
+  dim3 grid(unsigned(p.blocks)), block(kBlock);
+  if (partial)
+    hipLaunchKernelGGL((expect_kernel<R, RPT, G, CHK, KC, false, DM>), grid, block, 0, ctx->stream, da, src, p.map, v,
+                       psi, x, partial);
+  else
+    hipLaunchKernelGGL((spmv_kernel<R, RPT, G, CHK, KC, NT, DM>), grid, block, 0, ctx->stream, da, src, p.map, v, x, y);
+}
+
+template <typename R, int RPT, int G, bool CHK>
+void launch_kc(diaq_ctx* ctx, const DiagArgs& da, const DiagSrc& src, const Plan& p,
+               const typename Vec<R>::V* v, const typename Vec<R>::V* x, typename Vec<R>::V* y, double2* partial,
+               const typename Vec<R>::V* psi) {
+  if (p.kc == 3) {
+    if (p.nt) launch_one<R, RPT, G, CHK, 3, true, false>(ctx, da, src, p, v, x, y, partial, psi);
+    else launch_one<R, RPT, G, CHK, 3, false, false>(ctx, da, src, p, v, x, y, partial, psi);
+  } else {
+    if (p.nt) launch_one<R, RPT, G, CHK, 1, true, false>(ctx, da, src, p, v, x, y, partial, psi);
+    else launch_one<R, RPT, G, CHK, 1, false, false>(ctx, da, src, p, v, x, y, partial, psi);
+  }
+}
+
 template <typename R>
 diaq_status_t launch_typed(diaq_ctx* ctx, const SpmvOp& op, const DiagArgs& da, const DiagSrc& src,
                            const Plan& p, const void* vals, const void* x, void* y, double2* partial,
@@ -369,33 +462,23 @@ diaq_status_t launch_typed(diaq_ctx* ctx, const SpmvOp& op, const DiagArgs& da, 
   using V = typename Vec<R>::V;
   const V* v = static_cast<const V*>(vals);
   const V* xx = static_cast<const V*>(x);
-  dim3 grid(unsigned(p.blocks)), block(kBlock);
-#define DIAQ_LAUNCH(RPT, G, CHK)                                                                 \
-  do {                                                                                           \
-    if (partial)                                                                                 \
-      hipLaunchKernelGGL((expect_kernel<R, RPT, G, CHK>), grid, block, 0, ctx->stream, da, src,  \
-                         p.map, v, static_cast<const V*>(psi), xx, partial);                     \
-    else                                                                                         \
-      hipLaunchKernelGGL((spmv_kernel<R, RPT, G, CHK>), grid, block, 0, ctx->stream, da, src,    \
-                         p.map, v, xx, static_cast<V*>(y));                                      \
-  } while (0)
-  if (p.check) {
-    DIAQ_LAUNCH(1, 1, true);
-  } else if (p.g == 1) {
-    if (p.rpt == 4) DIAQ_LAUNCH(4, 1, false);
-    else if (p.rpt == 2) DIAQ_LAUNCH(2, 1, false);
-    else DIAQ_LAUNCH(1, 1, false);
-  } else if (p.g == 2) {
-    if (p.rpt == 4) DIAQ_LAUNCH(4, 2, false);
-    else if (p.rpt == 2) DIAQ_LAUNCH(2, 2, false);
-    else DIAQ_LAUNCH(1, 2, false);
-  } else if (p.g == 4) {
-    if (p.rpt == 2) DIAQ_LAUNCH(2, 4, false);
-    else DIAQ_LAUNCH(1, 4, false);
-  } else {
-    DIAQ_LAUNCH(1, 8, false);
-  }
-#undef DIAQ_LAUNCH
+  V* yy = static_cast<V*>(y);
+  const V* pp = static_cast<const V*>(psi);
+  const int rows = p.rpt * p.g;
+  if (src.dmeta) {
+    // many diagonals: device descriptor table, no tile grouping
+    if (p.check) launch_one<R, 1, 1, true, 3, false, true>(ctx, da, src, p, v, xx, yy, partial, pp);
+    else if (p.nt) launch_one<R, 2, 1, false, 3, true, true>(ctx, da, src, p, v, xx, yy, partial, pp);
+    else launch_one<R, 2, 1, false, 3, false, true>(ctx, da, src, p, v, xx, yy, partial, pp);
+  } else if (p.check) launch_kc<R, 1, 1, true>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else if (p.g == 1 && p.rpt == 4) launch_kc<R, 4, 1, false>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else if (p.g == 1 && p.rpt == 2) launch_kc<R, 2, 1, false>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else if (p.g == 1) launch_kc<R, 1, 1, false>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else if (p.g == 2 && p.rpt == 2) launch_kc<R, 2, 2, false>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else if (p.g == 2) launch_kc<R, 1, 2, false>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else if (p.g == 4) launch_kc<R, 1, 4, false>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else if (p.g == 8 && rows == 8) launch_one<R, 1, 8, false, 1, false, false>(ctx, da, src, p, v, xx, yy, partial, pp);
+  else return fail(DIAQ_ERR_DEVICE, "no SpMV variant for rows %d group %d", p.rpt, p.g);
   DIAQ_HIP(hipGetLastError());
   return DIAQ_OK;
 }
@@ -445,7 +528,7 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
   DiagArgs da;
   DiagSrc src;
   DIAQ_TRY(prepare(op, da, src));
-  const Plan p = plan_rows(op, ctx->spmv_rows);
+  const Plan p = plan_rows(op, ctx->tuning, ctx->spmv_rows);
   if (op.dtype == DIAQ_C128) return launch_typed<double>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
   return launch_typed<float>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
 }
@@ -465,7 +548,7 @@ diaq_status_t launch_expect(diaq_ctx* ctx, const SpmvOp& op, const void* psi, co
   DiagArgs da;
   DiagSrc src;
   DIAQ_TRY(prepare(op, da, src));
-  const Plan p = plan_rows(op, ctx->spmv_rows);
+  const Plan p = plan_rows(op, ctx->tuning, ctx->spmv_rows);
   DIAQ_TRY(ensure(ctx, &ctx->red, size_t(p.blocks) * sizeof(double2)));
   double2* partial = static_cast<double2*>(ctx->red.ptr);
   if (op.dtype == DIAQ_C128)

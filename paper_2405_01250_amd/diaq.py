@@ -52,6 +52,13 @@ class diaq_plan_t(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 3)]
 
 
+class diaq_tuning_t(ctypes.Structure):
+    _fields_ = [("spmv_rows", ctypes.c_int32), ("spmv_group_bits", ctypes.c_int32), ("spmv_chunk", ctypes.c_int32),
+                ("spmv_nontemporal", ctypes.c_int32), ("spmv_group_min_qubit", ctypes.c_int32),
+                ("expand_nontemporal", ctypes.c_int32), ("diag_pad", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
+
+
 class diaq_profile_t(ctypes.Structure):
     _fields_ = [("expand_launches", ctypes.c_int64), ("expand_ms", ctypes.c_double),
                 ("expand_bytes", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
@@ -91,6 +98,8 @@ _SIGS = {
     "diaq_expect": [_P, _P, _P, _P, ctypes.POINTER(_D)],
     "diaq_adjoint_grad": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _P, _P, _P, _I64,
                           ctypes.POINTER(_D), ctypes.POINTER(_D)],
+    "diaq_set_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
+    "diaq_get_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
     "diaq_profile_start": [_P],
     "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
@@ -430,6 +439,24 @@ def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: in
                                     _P(work.data_ptr()), nparams, ctypes.byref(e),
                                     grad.ctypes.data_as(ctypes.POINTER(_D))))
     return e.value, grad[:nparams]
+
+
+def set_tuning(ctx: Context | None = None, **knobs):
+    """Set product-kernel knobs (spmv_rows, spmv_group_bits, spmv_chunk,
+    spmv_nontemporal); unnamed knobs keep their current value."""
+    ctx = ctx or context()
+    t = diaq_tuning_t()
+    _check(load().diaq_get_tuning(ctx.handle, ctypes.byref(t)))
+    for k, v in knobs.items():
+        setattr(t, k, int(v))
+    _check(load().diaq_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def get_tuning(ctx: Context | None = None) -> dict:
+    ctx = ctx or context()
+    t = diaq_tuning_t()
+    _check(load().diaq_get_tuning(ctx.handle, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in diaq_tuning_t._fields_ if f != "reserved"}
 
 
 def profile_start(ctx: Context | None = None):
