@@ -216,6 +216,7 @@ def main():
         out["check"]["error"] = "norm drifted"
 
     if a.extras:
+        out["fused"] = [fused_extra(D, gates, state, scratch, ctx, n, k, a.steps) for k in (2, 3)]
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
     if a.cpu_seconds > 0:
         del state, scratch, Hzz
@@ -223,6 +224,28 @@ def main():
         eb = {id(g): s * e + s * (e + 2 * N) for g, e in zip(gates, E)}
         out["cpu_baseline"] = cpu_baseline(n, gates, a.cpu_seconds, lambda g: eb[id(g)])
     print(json.dumps(out), flush=True)
+
+
+def fused_extra(D, gates, state, scratch, ctx, n, kmax, steps):
+    """The same circuit with gate-level fusion (plan.fuse): logical gates/s
+    and the algorithmic rate of the fused operations."""
+    import torch
+    plan = D.make_plan(fuse=True, max_fused_qubits=kmax)
+    nops, nbytes = D.plan_count(gates, n, plan)
+    arr = D.gate_array(gates)
+    D.apply_circuit(gates, state, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    D.profile_start(ctx)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        D.apply_circuit(gates, state, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = D.profile_stop(ctx)
+    return {"max_fused_qubits": kmax, "ops": nops, "gates": len(gates), "ms_per_step": round(dt / steps * 1e3, 3),
+            "gates_per_s": round(len(gates) * steps / dt, 2), "GBps": round(nbytes * steps / dt / 1e9, 1),
+            "spmv_GBps": round(prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9, 1),
+            "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)}
 
 
 def adjoint_extra(D, W, torch, dev):

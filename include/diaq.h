@@ -261,6 +261,15 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                  void* state, void* scratch,
                                  const diaq_plan_t* plan);
 
+/* Host-only: the number of expansion + product launches (operations)
+ * diaq_apply_circuit issues for `gates` under `plan`, and the algorithmic
+ * bytes they move (expansion writes plus product reads and writes, the
+ * sum over operations of s * (2E + 2N)).  Either output may be NULL. */
+diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates,
+                              int32_t nqubits, diaq_dtype_t dtype,
+                              const diaq_plan_t* plan, int64_t* nops,
+                              double* bytes);
+
 /* Expectation value <psi|H|phi> (phi = NULL means phi = psi) written to
  * out[0] (real part) and out[1] (imaginary part), host memory.  The sum is
  * reduced in a fixed order, so repeated calls are bitwise equal.

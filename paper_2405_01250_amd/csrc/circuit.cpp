@@ -46,12 +46,12 @@ std::vector<int64_t> workspace_starts(const diaq_ctx* ctx, const std::vector<int
 }
 
 diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t>& offs, int n, diaq_dtype_t dt,
-                   bool adjoint, void** x, void** y) {
+                   bool adjoint, void** x, void** y, const DiagFactor* factors = nullptr, int nf = 0) {
   const std::vector<int64_t> st = workspace_starts(ctx, offs, n);
   const double s = double(elem_bytes(dt));
   const double E = double(packing_starts(offs, n).back()), N = double(int64_t(1) << n);
   const size_t e0 = prof_mark(ctx);
-  DIAQ_TRY(launch_expand(ctx, lg, n, dt, offs, st, ctx->diag.ptr));
+  DIAQ_TRY(launch_expand(ctx, lg, n, dt, offs, st, ctx->diag.ptr, factors, nf));
   const size_t e1 = prof_mark(ctx);
   prof_interval(ctx, e0, e1, 0, s * E);
   struct Close {
@@ -104,6 +104,41 @@ diaq_status_t run_plain(diaq_ctx* ctx, const Prepared& p, int64_t begin, int64_t
   return DIAQ_OK;
 }
 
+// Fused forward pass: one expansion + product per planned op.
+diaq_status_t run_fused(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, diaq_dtype_t dt, void* state,
+                        void* scratch, void** result) {
+  std::vector<std::vector<int64_t>> offs(ops.size());
+  std::vector<DiagFactor> table;
+  std::vector<size_t> first(ops.size());
+  int64_t max_values = 0;
+  for (size_t k = 0; k < ops.size(); k++) {
+    offs[k] = gate_offsets(ops[k].core);
+    if (offs[k].size() > size_t(kMaxArgDiags))
+      return fail(DIAQ_ERR_UNSUPPORTED, "fused op %zu has %zu diagonals", k, offs[k].size());
+    max_values = std::max<int64_t>(max_values, packing_starts(offs[k], n).back());
+    first[k] = table.size();
+    table.insert(table.end(), ops[k].post.begin(), ops[k].post.end());
+  }
+  const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
+  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(max_values + (kMaxArgDiags + 1) * pad) * elem_bytes(dt)));
+  DiagFactor* dtab = nullptr;
+  if (!table.empty()) {
+    DIAQ_TRY(ensure(ctx, &ctx->aux, table.size() * sizeof(DiagFactor)));
+    dtab = static_cast<DiagFactor*>(ctx->aux.ptr);
+    // synchronous: the host table dies with this call
+    DIAQ_HIP(hipStreamSynchronize(ctx->stream));
+    DIAQ_HIP(hipMemcpy(dtab, table.data(), table.size() * sizeof(DiagFactor), hipMemcpyHostToDevice));
+  }
+  void* x = state;
+  void* y = scratch;
+  for (size_t k = 0; k < ops.size(); k++) {
+    const int nf = int(ops[k].post.size());
+    DIAQ_TRY(step(ctx, ops[k].core, offs[k], n, dt, false, &x, &y, nf ? dtab + first[k] : nullptr, nf));
+  }
+  *result = x;
+  return DIAQ_OK;
+}
+
 }  // namespace diaq
 
 using namespace diaq;
@@ -120,18 +155,54 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "gate range [%lld, %lld) outside [0, %lld]", (long long)begin,
                   (long long)end, (long long)ngates);
     DIAQ_TRY(check_vectors(nqubits, dtype, state, scratch));
-    if (plan && (plan->fuse || plan->kron)) return fail(DIAQ_ERR_UNSUPPORTED, "plan options not built yet");
-    Prepared p;
-    DIAQ_TRY(prepare_gates(gates + begin, end - begin, nqubits, &p));
+    if (plan && plan->kron) return fail(DIAQ_ERR_UNSUPPORTED, "plan option kron not built yet");
     const int saved_rows = ctx->spmv_rows;
     if (plan && plan->rows_per_thread) ctx->spmv_rows = plan->rows_per_thread;
     void* res = nullptr;
-    diaq_status_t st = run_plain(ctx, p, 0, end - begin, nqubits, dtype, state, scratch, &res);
+    diaq_status_t st;
+    if (plan && plan->fuse) {
+      std::vector<FusedOp> ops;
+      st = plan_fusion(gates + begin, end - begin, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2,
+                       dtype, &ops);
+      if (st == DIAQ_OK) st = run_fused(ctx, ops, nqubits, dtype, state, scratch, &res);
+    } else {
+      Prepared p;
+      st = prepare_gates(gates + begin, end - begin, nqubits, &p);
+      if (st == DIAQ_OK) st = run_plain(ctx, p, 0, end - begin, nqubits, dtype, state, scratch, &res);
+    }
     ctx->spmv_rows = saved_rows;
     DIAQ_TRY(st);
     if (res != state)
       DIAQ_HIP(hipMemcpyAsync(state, res, (size_t(1) << nqubits) * elem_bytes(dtype), hipMemcpyDeviceToDevice,
                               ctx->stream));
+    return DIAQ_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates, int32_t nqubits, diaq_dtype_t dtype,
+                              const diaq_plan_t* plan, int64_t* nops, double* bytes) {
+  try {
+    if (ngates < 0 || (ngates > 0 && !gates)) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad gate list");
+    if (dtype != DIAQ_C64 && dtype != DIAQ_C128) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad dtype");
+    const double s = double(elem_bytes(dtype)), N = double(int64_t(1) << nqubits);
+    double b = 0;
+    int64_t count = 0;
+    if (plan && plan->fuse) {
+      std::vector<FusedOp> ops;
+      DIAQ_TRY(plan_fusion(gates, ngates, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2, dtype,
+                           &ops));
+      for (const auto& op : ops) b += s * (2.0 * double(packing_starts(gate_offsets(op.core), nqubits).back()) + 2 * N);
+      count = int64_t(ops.size());
+    } else {
+      Prepared p;
+      DIAQ_TRY(prepare_gates(gates, ngates, nqubits, &p));
+      for (const auto& o : p.offs) b += s * (2.0 * double(packing_starts(o, nqubits).back()) + 2 * N);
+      count = ngates;
+    }
+    if (nops) *nops = count;
+    if (bytes) *bytes = b;
     return DIAQ_OK;
   } catch (const std::bad_alloc&) {
     return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");

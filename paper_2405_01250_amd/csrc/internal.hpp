@@ -123,6 +123,34 @@ std::vector<int64_t> packing_starts(const std::vector<int64_t>& offs, int n);
 bool is_diagonal_kind(const diaq_gate_t* g);
 
 // ---------------------------------------------------------------------------
+// Gate-level fusion (planner.cpp)
+// ---------------------------------------------------------------------------
+
+// A diagonal gate folded into an expansion: the expanded element (i, j) is
+// multiplied by v[loc(i)], loc gathering the bits of q[0..k) (q[0] = LSB).
+struct DiagFactor {
+  int32_t k;
+  int32_t q[3];
+  double v[8][2];
+};
+
+// One expansion + product: a core gate (targets, controls, local matrix)
+// followed by diagonal gates applied after it.
+struct FusedOp {
+  LocalGate core;
+  std::vector<DiagFactor> post;
+  int64_t ngates = 0;  // logical gates folded in
+};
+
+// Greedy gate-level fusion: a gate joins the latest op sharing one of its
+// qubits (it commutes with every later op) when the product of the local
+// matrices (Alg. 1 on the local DiaQ diagonals) spans at most kmax qubits
+// and does not move more bytes than the two applied separately; a
+// diagonal gate that cannot join the core is folded in as a post factor.
+diaq_status_t plan_fusion(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, diaq_dtype_t dt,
+                          std::vector<FusedOp>* ops);
+
+// ---------------------------------------------------------------------------
 // Kernel launchers (one .hip file each)
 // ---------------------------------------------------------------------------
 
@@ -136,10 +164,12 @@ struct DiagArgs {
   int64_t start[kMaxArgDiags];
 };
 
-// expand.hip
+// expand.hip.  `factors` (device, nf entries) are diagonal gates applied
+// after the core gate (nullptr / 0: none).
 diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n,
                             diaq_dtype_t dt, const std::vector<int64_t>& offs,
-                            const std::vector<int64_t>& starts, void* values);
+                            const std::vector<int64_t>& starts, void* values,
+                            const DiagFactor* factors = nullptr, int nf = 0);
 diaq_status_t launch_pauli_dia(diaq_ctx* ctx, int n, diaq_dtype_t dt,
                                const std::vector<int64_t>& offs,
                                const std::vector<int64_t>& starts,

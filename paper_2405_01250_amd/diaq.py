@@ -100,6 +100,8 @@ _SIGS = {
                           ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "diaq_set_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
     "diaq_get_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
+    "diaq_plan_count": [ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, ctypes.POINTER(diaq_plan_t),
+                        ctypes.POINTER(_I64), ctypes.POINTER(_D)],
     "diaq_profile_start": [_P],
     "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
@@ -492,3 +494,15 @@ class DiaqExpectation(torch.autograd.Function):
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         return grad_out * g, None, None, None
+
+
+def plan_count(gates: Sequence, n: int, plan: diaq_plan_t | None = None, dtype=torch.complex128):
+    """(operations, algorithmic bytes) diaq_apply_circuit issues for `gates`
+    under `plan` (host-only, no GPU needed)."""
+    arr, keep = gate_array(gates)
+    nops = _I64()
+    b = _D()
+    _check(load().diaq_plan_count(arr, len(gates), n, _dtype_code(dtype),
+                                  ctypes.byref(plan) if plan is not None else None, ctypes.byref(nops),
+                                  ctypes.byref(b)))
+    return nops.value, b.value

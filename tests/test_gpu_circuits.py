@@ -182,3 +182,43 @@ def test_autograd_function():
     E.backward()
     ps = orc.param_shift_grad(W.zero_state(n), n, gates, terms, len(theta))
     assert np.allclose(th.grad.numpy(), ps, atol=1e-10, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# Gate-level fusion (plan.fuse)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kmax", [1, 2, 3])
+@pytest.mark.parametrize("seed", range(4))
+def test_fused_random_circuits_match_oracle(kmax, seed):
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(2, 13))
+    gates = [_random_gate(rng, n) for _ in range(int(rng.integers(5, 60)))]
+    x = W.random_state(n, seed)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi, plan=D.make_plan(fuse=True, max_fused_qubits=kmax))
+    assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "fused k=%d seed %d" % (kmax, seed))
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3])
+def test_fused_workloads_match_oracle(kmax):
+    plan = D.make_plan(fuse=True, max_fused_qubits=kmax)
+    cases = [("qft", 14, W.qft(14), W.random_state(14, 1)),
+             ("random_layered", 14, W.random_layered(14, 6, 3), W.zero_state(14)),
+             ("hea", 12, W.hea(12, 3, 2)[0], W.zero_state(12)),
+             ("tfim", 12, W.tfim(12, 5), W.random_state(12, 4)),
+             ("ghz", 12, W.ghz(12), W.zero_state(12))]
+    for name, n, gates, x in cases:
+        nops, _ = D.plan_count(gates, n, plan)
+        assert nops <= len(gates)
+        psi = to_dev(x)
+        D.apply_circuit(gates, psi, plan=plan)
+        assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "%s k=%d" % (name, kmax))
+
+
+def test_fused_qft_n20_against_ifft():
+    n = 20
+    x = W.random_state(n, 20)
+    psi = to_dev(x)
+    D.apply_circuit(W.qft(n), psi, plan=D.make_plan(fuse=True, max_fused_qubits=2))
+    assert_state_close(to_host(psi), np.fft.ifft(x, norm="ortho"), TOL64, "fused QFT-20")
