@@ -218,6 +218,7 @@ def main():
     if a.extras:
         out["fused"] = [fused_extra(D, gates, state, scratch, ctx, n, k, a.steps) for k in (2, 3)]
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
+        out["batch"] = batch_extra(D, W, torch, dev)
     if a.cpu_seconds > 0:
         del state, scratch, Hzz
         torch.cuda.empty_cache()
@@ -246,6 +247,49 @@ def fused_extra(D, gates, state, scratch, ctx, n, kmax, steps):
             "gates_per_s": round(len(gates) * steps / dt, 2), "GBps": round(nbytes * steps / dt / 1e9, 1),
             "spmv_GBps": round(prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9, 1),
             "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)}
+
+
+def batch_extra(D, W, torch, dev, reps=3):
+    """512 QAOA circuits (widths 10..22, p 1..4): one persistent launch
+    (eager and graph-replayed) against the plain per-gate path (expansion +
+    SpMV per gate, adjoint sweep per circuit)."""
+    import numpy as np
+    insts = W.qaoa_batch(512, 512)
+    circs = [(i.n, i.gates, i.terms, 2 * i.p) for i in insts]
+    theta = np.concatenate([np.ravel(np.column_stack([i.gammas, i.betas])) for i in insts])
+    out = {"workload": "512 MaxCut QAOA circuits, widths {10..22}, 3-regular graphs, p in 1..4, seed 512",
+           "circuits": len(insts), "params": int(theta.size)}
+    for graph in (False, True):
+        b = D.Batch(circs, graph=graph)
+        ev, gr = b.run(theta)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ev, gr = b.run(theta)
+        dt = (time.perf_counter() - t0) / reps
+        key = "graph" if graph else "eager"
+        out[key + "_ms"] = round(dt * 1e3, 2)
+        out[key + "_circuits_per_s"] = round(len(insts) / dt, 1)
+        del b
+    # plain per-gate path: every circuit through diaq_adjoint_grad
+    mats = [D.from_pauli_sum(i.n, i.terms) for i in insts]
+    work = torch.empty(3 << 22, dtype=torch.complex128, device=dev)
+    psi0s = {}
+    for i in insts:
+        if i.n not in psi0s:
+            p = torch.zeros(1 << i.n, dtype=torch.complex128, device=dev)
+            p[0] = 1
+            psi0s[i.n] = p
+    max_err = 0.0
+    t0 = time.perf_counter()
+    for k, i in enumerate(insts):
+        e, g = D.adjoint_grad(i.gates, mats[k], psi0s[i.n], 2 * i.p, work=work[: 3 << i.n])
+        max_err = max(max_err, abs(e - ev[k]), float(np.max(np.abs(g - gr[k]))))
+    dt = time.perf_counter() - t0
+    out["plain_per_gate_ms"] = round(dt * 1e3, 2)
+    out["plain_circuits_per_s"] = round(len(insts) / dt, 1)
+    out["speedup_graph_vs_plain"] = round(dt * 1e3 / out["graph_ms"], 1)
+    out["max_abs_diff_vs_plain"] = max_err
+    return out
 
 
 def adjoint_extra(D, W, torch, dev):

@@ -292,6 +292,49 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                 double* grad);
 
 /* ------------------------------------------------------------------ */
+/* Batched circuits: one persistent launch, optionally a captured graph  */
+/* ------------------------------------------------------------------ */
+
+/* One circuit of a batch.  It starts from |0...0>; every gate acts on at
+ * most 2 targets plus at most 2 controls.  The observable is diagonal:
+ * H = sum_t coef[t] * Z^{zmask[t]} (zmask = 0 is the identity term), as
+ * for MaxCut-type cost functions.  A differentiable gate (param_index >= 0)
+ * takes the angle param_scale * theta[param_index] when diaq_batch_run is
+ * given theta, else params[0]; gradients are per circuit, nparams each. */
+typedef struct diaq_circuit {
+  int32_t nqubits;  /* 1..30 */
+  int32_t nparams;
+  int64_t ngates;
+  const diaq_gate_t* gates; /* host */
+  int32_t nterms;
+  int32_t reserved;
+  const uint64_t* zmask;    /* host, nterms */
+  const double* coef;       /* host, nterms */
+} diaq_circuit_t;
+
+typedef struct diaq_batch* diaq_batch_t;
+
+#define DIAQ_BATCH_GRAPH 1u /* capture upload + kernel + download in a
+                               hipGraph once and replay it on every run */
+
+/* Upload a batch: gate tables, observables and per-circuit state vectors
+ * (two of 2^n elements per circuit, complex128) are placed in device memory
+ * owned by the handle. */
+diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits,
+                                int32_t ncircuits, uint32_t flags,
+                                diaq_batch_t* out);
+/* Run every circuit of the batch in one persistent launch: forward pass,
+ * E_c = <psi_c|H_c|psi_c>, and the adjoint reverse sweep for dE_c/dtheta.
+ * theta (host, sum of nparams entries, circuit-major) may be NULL.
+ * Writes expvals[ncircuits] and grads[sum nparams] (host).  Workgroups
+ * take whole circuits from a device queue in decreasing order of work; a
+ * circuit of at most 12 qubits keeps both of its vectors in LDS.
+ * Synchronises the stream. */
+diaq_status_t diaq_batch_run(diaq_batch_t batch, const double* theta,
+                             double* expvals, double* grads);
+diaq_status_t diaq_batch_free(diaq_batch_t batch);
+
+/* ------------------------------------------------------------------ */
 /* Tuning knobs of the product kernel (set by the autotuner)            */
 /* ------------------------------------------------------------------ */
 

@@ -45,7 +45,7 @@ void orc_apply_gate(double *psi, int n, const double *m, int k,
             if ((r >> j) & 1) s |= (int64_t)1 << targets[j];
         sc[r] = s;
     }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N > 32768)
     for (int64_t b = 0; b < N; b++) {
         if ((b & tmask) != 0 || (b & cmask) != cmask) continue;
         double vr[8], vi[8];
@@ -131,7 +131,7 @@ void orc_pauli_sum_apply(int n, int nterms, const uint64_t *xmask,
                          const double *phi, double *out)
 {
     const int64_t N = (int64_t)1 << n;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N > 32768)
     for (int64_t i = 0; i < N; i++) {
         double ar = 0.0, ai = 0.0;
         for (int t = 0; t < nterms; t++) {

@@ -102,6 +102,9 @@ _SIGS = {
     "diaq_get_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
     "diaq_plan_count": [ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, ctypes.POINTER(diaq_plan_t),
                         ctypes.POINTER(_I64), ctypes.POINTER(_D)],
+    "diaq_batch_create": [_P, _P, _I32, _U32, ctypes.POINTER(_P)],
+    "diaq_batch_run": [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)],
+    "diaq_batch_free": [_P],
     "diaq_profile_start": [_P],
     "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
@@ -506,3 +509,75 @@ def plan_count(gates: Sequence, n: int, plan: diaq_plan_t | None = None, dtype=t
                                   ctypes.byref(plan) if plan is not None else None, ctypes.byref(nops),
                                   ctypes.byref(b)))
     return nops.value, b.value
+
+
+# --------------------------------------------------------------------------
+# Batched circuits (one persistent launch, optional hipGraph replay)
+# --------------------------------------------------------------------------
+
+class diaq_circuit_t(ctypes.Structure):
+    _fields_ = [("nqubits", ctypes.c_int32), ("nparams", ctypes.c_int32), ("ngates", ctypes.c_int64),
+                ("gates", ctypes.POINTER(diaq_gate_t)), ("nterms", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("zmask", ctypes.POINTER(ctypes.c_uint64)), ("coef", ctypes.POINTER(ctypes.c_double))]
+
+
+BATCH_GRAPH = 1
+
+
+class Batch:
+    """Circuits uploaded once and run together: ``run(theta)`` returns the
+    expectation values and the per-circuit adjoint gradients.
+
+    ``circuits`` is a list of (nqubits, gates, terms, nparams) where terms
+    are diagonal Pauli strings (xmask must be 0)."""
+
+    def __init__(self, circuits, graph: bool = False, ctx: Context | None = None):
+        self.ctx = ctx or context()
+        self._keep = []
+        arr = (diaq_circuit_t * max(1, len(circuits)))()
+        self.nparams = []
+        for i, (n, gates, terms, nparams) in enumerate(circuits):
+            garr, keep = gate_array(gates)
+            if any(t[0] for t in terms):
+                raise ValueError("batched observables must be diagonal (xmask = 0)")
+            zm = np.ascontiguousarray(np.array([t[1] for t in terms], dtype=np.uint64))
+            cf = np.ascontiguousarray(np.array([t[2] for t in terms], dtype=np.float64))
+            self._keep += [garr, keep, zm, cf]
+            c = arr[i]
+            c.nqubits, c.nparams, c.ngates = n, nparams, len(gates)
+            c.gates = ctypes.cast(garr, ctypes.POINTER(diaq_gate_t))
+            c.nterms = len(terms)
+            c.zmask = zm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+            c.coef = cf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self.nparams.append(nparams)
+        self.ncirc = len(circuits)
+        h = _P()
+        _check(load().diaq_batch_create(self.ctx.handle, arr, len(circuits), BATCH_GRAPH if graph else 0,
+                                        ctypes.byref(h)))
+        self.handle = h
+        self._keep = []  # the library copied everything
+
+    def run(self, theta=None):
+        ev = np.zeros(max(1, self.ncirc))
+        gr = np.zeros(max(1, sum(self.nparams)))
+        tp = None
+        if theta is not None:
+            th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+            if th.size != sum(self.nparams):
+                raise ValueError("theta needs %d entries" % sum(self.nparams))
+            tp = th.ctypes.data_as(ctypes.POINTER(_D))
+        _check(load().diaq_batch_run(self.handle, tp, ev.ctypes.data_as(ctypes.POINTER(_D)),
+                                     gr.ctypes.data_as(ctypes.POINTER(_D))))
+        out, k = [], 0
+        for p in self.nparams:
+            out.append(gr[k:k + p].copy())
+            k += p
+        return ev[:self.ncirc].copy(), out
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.diaq_batch_free(self.handle)
+        except Exception:
+            pass
+        self.handle = None
