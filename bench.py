@@ -216,7 +216,10 @@ def main():
         out["check"]["error"] = "norm drifted"
 
     if a.extras:
-        out["fused"] = [fused_extra(D, gates, state, scratch, ctx, n, k, a.steps) for k in (2, 3)]
+        out["variants"] = [fused_extra(D, gates, state, scratch, ctx, n, a.steps, **kw)
+                           for kw in ({"fuse": True, "max_fused_qubits": 2}, {"fuse": True, "max_fused_qubits": 3},
+                                      {"kron": True}, {"kron": True, "fuse": True, "max_fused_qubits": 2},
+                                      {"kron": True, "fuse": True, "max_fused_qubits": 3})]
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
         out["batch"] = batch_extra(D, W, torch, dev)
     if a.cpu_seconds > 0:
@@ -227,11 +230,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def fused_extra(D, gates, state, scratch, ctx, n, kmax, steps):
-    """The same circuit with gate-level fusion (plan.fuse): logical gates/s
-    and the algorithmic rate of the fused operations."""
+def fused_extra(D, gates, state, scratch, ctx, n, steps, **kw):
+    """The same circuit under another plan -- gate-level fusion (plan.fuse)
+    and/or Alg. 3 in-place products (plan.kron): logical gates/s and the
+    algorithmic rate of the operations actually run."""
     import torch
-    plan = D.make_plan(fuse=True, max_fused_qubits=kmax)
+    plan = D.make_plan(**kw)
+    kmax = kw.get("max_fused_qubits", 0)
     nops, nbytes = D.plan_count(gates, n, plan)
     arr = D.gate_array(gates)
     D.apply_circuit(gates, state, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
@@ -243,10 +248,12 @@ def fused_extra(D, gates, state, scratch, ctx, n, kmax, steps):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = D.profile_stop(ctx)
-    return {"max_fused_qubits": kmax, "ops": nops, "gates": len(gates), "ms_per_step": round(dt / steps * 1e3, 3),
+    return {"plan": ("kron" if kw.get("kron") else "dia") + ("+fuse%d" % kmax if kw.get("fuse") else ""),
+            "ops": nops, "gates": len(gates), "ms_per_step": round(dt / steps * 1e3, 3),
             "gates_per_s": round(len(gates) * steps / dt, 2), "GBps": round(nbytes * steps / dt / 1e9, 1),
-            "spmv_GBps": round(prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9, 1),
-            "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)}
+            "product_GBps": round(prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9, 1) if prof["spmv_ms"] else None,
+            "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)
+            if prof["expand_ms"] else None}
 
 
 def batch_extra(D, W, torch, dev, reps=3):
@@ -319,11 +326,19 @@ def adjoint_extra(D, W, torch, dev):
         D.apply_circuit(gates, psi, scratch=scratch, marshalled=arr)
         D.expect(H, psi)
     t_fwd = (time.perf_counter() - t0) / reps
+    kplan = D.make_plan(kron=True)
+    D.adjoint_grad(gates, H, psi0, len(theta), work=work, plan=kplan)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ek, gk = D.adjoint_grad(gates, H, psi0, len(theta), work=work, plan=kplan)
+    t_kadj = (time.perf_counter() - t0) / reps
     return {"workload": "HEA n=20, 8 layers (RY, RZ, CZ ring), 320 params, H = sum a ZZ + sum b X",
             "adjoint_grads_per_s": round(1 / t_adj, 3), "adjoint_ms": round(t_adj * 1e3, 2),
             "forward_ms": round(t_fwd * 1e3, 2),
             "param_shift_grads_per_s": round(1 / (2 * len(theta) * t_fwd), 4),
             "speedup_vs_param_shift": round(2 * len(theta) * t_fwd / t_adj, 1),
+            "kron_adjoint_grads_per_s": round(1 / t_kadj, 3), "kron_adjoint_ms": round(t_kadj * 1e3, 2),
+            "kron_max_abs_grad_diff": float(abs(gk - g).max()),
             "energy": e}
 
 

@@ -283,13 +283,16 @@ diaq_status_t diaq_expect(diaq_ctx_t ctx, diaq_dia_t H, const void* psi,
  * differentiable gate and steps psi and lambda back through U_g^dagger (the
  * conjugate-transposed DiaQ matrix of the same expansion).  `work` holds
  * 3 * 2^n elements of device memory.  Writes *expval and grad[0..nparams)
- * (host, zeroed first).  Synchronises the stream. */
+ * (host, zeroed first).  plan == NULL (or kron == 0): every gate and every
+ * U^dagger is expanded and applied by Alg. 2; plan->kron: gates are applied
+ * in place by Alg. 3 and each reverse step is one fused pass (dot, then
+ * both vectors stepped back).  Synchronises the stream. */
 diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                 int64_t ngates, int32_t nqubits,
                                 diaq_dtype_t dtype, diaq_dia_t H,
                                 const void* psi0, void* work,
                                 int64_t nparams, double* expval,
-                                double* grad);
+                                double* grad, const diaq_plan_t* plan);
 
 /* ------------------------------------------------------------------ */
 /* Batched circuits: one persistent launch, optionally a captured graph  */

@@ -139,6 +139,50 @@ diaq_status_t run_fused(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, d
   return DIAQ_OK;
 }
 
+// Copy the ops' folded diagonal factors into one device table; first[k] is
+// op k's first entry.
+diaq_status_t upload_factors(diaq_ctx* ctx, const std::vector<FusedOp>& ops, DiagFactor** dtab,
+                             std::vector<size_t>* first) {
+  std::vector<DiagFactor> table;
+  first->resize(ops.size());
+  for (size_t k = 0; k < ops.size(); k++) {
+    (*first)[k] = table.size();
+    table.insert(table.end(), ops[k].post.begin(), ops[k].post.end());
+  }
+  *dtab = nullptr;
+  if (table.empty()) return DIAQ_OK;
+  DIAQ_TRY(ensure(ctx, &ctx->aux, table.size() * sizeof(DiagFactor)));
+  *dtab = static_cast<DiagFactor*>(ctx->aux.ptr);
+  // synchronous: the host table dies with this call
+  DIAQ_HIP(hipStreamSynchronize(ctx->stream));
+  DIAQ_HIP(hipMemcpy(*dtab, table.data(), table.size() * sizeof(DiagFactor), hipMemcpyHostToDevice));
+  return DIAQ_OK;
+}
+
+// Alg. 3 forward pass: every op applied in place on `state`, no expansion.
+diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, diaq_dtype_t dt, void* state) {
+  DiagFactor* dtab = nullptr;
+  std::vector<size_t> first;
+  DIAQ_TRY(upload_factors(ctx, ops, &dtab, &first));
+  const double bytes = 2.0 * double(elem_bytes(dt)) * double(int64_t(1) << n);
+  for (size_t k = 0; k < ops.size(); k++) {
+    const int nf = int(ops[k].post.size());
+    const size_t e0 = prof_mark(ctx);
+    DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false, nf ? dtab + first[k] : nullptr, nf));
+    prof_interval(ctx, e0, prof_mark(ctx), 1, bytes);
+  }
+  return DIAQ_OK;
+}
+
+std::vector<FusedOp> unfused_ops(const Prepared& p) {
+  std::vector<FusedOp> ops(p.lg.size());
+  for (size_t k = 0; k < p.lg.size(); k++) {
+    ops[k].core = p.lg[k];
+    ops[k].ngates = 1;
+  }
+  return ops;
+}
+
 }  // namespace diaq
 
 using namespace diaq;
@@ -155,15 +199,25 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "gate range [%lld, %lld) outside [0, %lld]", (long long)begin,
                   (long long)end, (long long)ngates);
     DIAQ_TRY(check_vectors(nqubits, dtype, state, scratch));
-    if (plan && plan->kron) return fail(DIAQ_ERR_UNSUPPORTED, "plan option kron not built yet");
     const int saved_rows = ctx->spmv_rows;
     if (plan && plan->rows_per_thread) ctx->spmv_rows = plan->rows_per_thread;
     void* res = nullptr;
     diaq_status_t st;
-    if (plan && plan->fuse) {
+    const int kmax = plan && plan->max_fused_qubits ? plan->max_fused_qubits : 2;
+    if (plan && plan->kron) {
       std::vector<FusedOp> ops;
-      st = plan_fusion(gates + begin, end - begin, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2,
-                       dtype, &ops);
+      if (plan->fuse) {
+        st = plan_fusion(gates + begin, end - begin, nqubits, kmax, dtype, &ops, true);
+      } else {
+        Prepared p;
+        st = prepare_gates(gates + begin, end - begin, nqubits, &p);
+        if (st == DIAQ_OK) ops = unfused_ops(p);
+      }
+      if (st == DIAQ_OK) st = run_kron(ctx, ops, nqubits, dtype, state);
+      res = state;
+    } else if (plan && plan->fuse) {
+      std::vector<FusedOp> ops;
+      st = plan_fusion(gates + begin, end - begin, nqubits, kmax, dtype, &ops);
       if (st == DIAQ_OK) st = run_fused(ctx, ops, nqubits, dtype, state, scratch, &res);
     } else {
       Prepared p;
@@ -189,7 +243,19 @@ diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates, int32_t 
     const double s = double(elem_bytes(dtype)), N = double(int64_t(1) << nqubits);
     double b = 0;
     int64_t count = 0;
-    if (plan && plan->fuse) {
+    if (plan && plan->kron) {
+      if (plan->fuse) {
+        std::vector<FusedOp> ops;
+        DIAQ_TRY(plan_fusion(gates, ngates, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2, dtype,
+                             &ops, true));
+        count = int64_t(ops.size());
+      } else {
+        Prepared p;
+        DIAQ_TRY(prepare_gates(gates, ngates, nqubits, &p));
+        count = ngates;
+      }
+      b = double(count) * 2.0 * s * N;  // each op reads and writes the state once
+    } else if (plan && plan->fuse) {
       std::vector<FusedOp> ops;
       DIAQ_TRY(plan_fusion(gates, ngates, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2, dtype,
                            &ops));
@@ -211,7 +277,7 @@ diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates, int32_t 
 
 diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t ngates, int32_t nqubits,
                                 diaq_dtype_t dtype, diaq_dia_t H, const void* psi0, void* work, int64_t nparams,
-                                double* expval, double* grad) {
+                                double* expval, double* grad, const diaq_plan_t* plan) {
   try {
     if (!ctx || !H || !psi0 || !work || !expval || (nparams > 0 && !grad))
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
@@ -249,11 +315,16 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     double* dots = static_cast<double*>(ctx->aux.ptr);
     DIAQ_HIP(hipMemsetAsync(dots, 0, size_t(ngates + 1) * 2 * sizeof(double), ctx->stream));
 
+    const bool kron = plan && plan->kron;
     // forward: psi = U psi0
     DIAQ_HIP(hipMemcpyAsync(psi, psi0, vb, hipMemcpyDeviceToDevice, ctx->stream));
-    void* res = nullptr;
-    DIAQ_TRY(run_plain(ctx, p, 0, ngates, nqubits, dtype, psi, tmp, &res));
-    if (res != psi) std::swap(psi, tmp);
+    if (kron) {
+      DIAQ_TRY(run_kron(ctx, unfused_ops(p), nqubits, dtype, psi));
+    } else {
+      void* res = nullptr;
+      DIAQ_TRY(run_plain(ctx, p, 0, ngates, nqubits, dtype, psi, tmp, &res));
+      if (res != psi) std::swap(psi, tmp);
+    }
     // lam = H psi ; E = <psi|lam>
     DIAQ_TRY(launch_spmv(ctx, op_of(H, H->transposed, H->conjugated), psi, lam));
     LocalGate ident;
@@ -264,11 +335,27 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     ident.m[1][1][0] = 1;
     DIAQ_TRY(launch_generator_dot(ctx, ident, nqubits, dtype, psi, lam, dots));
     // reverse sweep
-    for (int64_t g = ngates - 1; g >= 0; g--) {
-      if (diff[g]) DIAQ_TRY(launch_generator_dot(ctx, gens[g], nqubits, dtype, lam, psi, dots + 2 * (g + 1)));
-      if (g == 0) break;
-      DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], nqubits, dtype, true, &psi, &tmp));
-      DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], nqubits, dtype, true, &lam, &tmp));
+    if (kron) {
+      // one fused Alg. 3 pass per gate: generator dot, then psi, lam <- U^dagger
+      int64_t maxb = 1;
+      for (int64_t g = 0; g < ngates; g++) maxb = std::max(maxb, kron_adjoint_blocks(p.lg[g], nqubits));
+      DIAQ_TRY(ensure(ctx, &ctx->red, size_t(maxb) * sizeof(double2)));
+      double2* partial = static_cast<double2*>(ctx->red.ptr);
+      for (int64_t g = ngates - 1; g >= 0; g--) {
+        if (!diff[g] && g == 0) break;
+        DIAQ_TRY(launch_kron_adjoint(ctx, ctx->stream, p.lg[g], diff[g] ? &gens[g] : nullptr, nqubits, dtype, psi,
+                                     lam, partial, g > 0));
+        if (diff[g])
+          DIAQ_TRY(launch_final_reduce(ctx->stream, partial, kron_adjoint_blocks(p.lg[g], nqubits),
+                                       dots + 2 * (g + 1)));
+      }
+    } else {
+      for (int64_t g = ngates - 1; g >= 0; g--) {
+        if (diff[g]) DIAQ_TRY(launch_generator_dot(ctx, gens[g], nqubits, dtype, lam, psi, dots + 2 * (g + 1)));
+        if (g == 0) break;
+        DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], nqubits, dtype, true, &psi, &tmp));
+        DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], nqubits, dtype, true, &lam, &tmp));
+      }
     }
     const size_t rb = size_t(ngates + 1) * 2 * sizeof(double);
     DIAQ_TRY(ensure_pinned(ctx, rb));

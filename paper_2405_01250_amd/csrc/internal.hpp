@@ -147,8 +147,10 @@ struct FusedOp {
 // matrices (Alg. 1 on the local DiaQ diagonals) spans at most kmax qubits
 // and does not move more bytes than the two applied separately; a
 // diagonal gate that cannot join the core is folded in as a post factor.
+// With kron = true the ops are applied in place by Alg. 3 (2 N s bytes
+// each, whatever their diagonals), so any merge within kmax qubits pays.
 diaq_status_t plan_fusion(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, diaq_dtype_t dt,
-                          std::vector<FusedOp>* ops);
+                          std::vector<FusedOp>* ops, bool kron = false);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (one .hip file each)
@@ -202,6 +204,18 @@ diaq_status_t launch_expect(diaq_ctx* ctx, const SpmvOp& op, const void* psi,
 diaq_status_t launch_generator_dot(diaq_ctx* ctx, const LocalGate& gen, int n,
                                    diaq_dtype_t dt, const void* lam,
                                    const void* psi, double* dres);
+
+// kron.hip: Alg. 3 products without expansion, in place on `v`.
+diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
+                                void* v, bool adjoint, const DiagFactor* factors = nullptr, int nf = 0);
+// Reverse-sweep step: optional generator dot (one double2 partial per
+// workgroup into `partial`, kron_adjoint_blocks of them), then
+// psi, lam <- U^dagger psi, U^dagger lam when step_back.
+int64_t kron_adjoint_blocks(const LocalGate& lg, int n);
+diaq_status_t launch_kron_adjoint(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, const LocalGate* gen,
+                                  int n, diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back);
+// spmv.hip: one workgroup sums partial[0..count) into dres (2 doubles).
+diaq_status_t launch_final_reduce(hipStream_t stream, const double2* partial, int64_t count, double* dres);
 
 // fuse.hip
 diaq_status_t fuse_dia(diaq_ctx* ctx, const diaq_dia* first,

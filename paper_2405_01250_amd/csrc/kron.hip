@@ -1,0 +1,338 @@
+// kron.hip -- Alg. 3: y = (I_a (x) M (x) I_b) x without expanding the gate.
+//
+// Alg. 3 walks M's DiaQ diagonals and, for each, multiplies the diagonal's
+// values into shifted subsets of x (offset dim_b * dIndex).  For targets
+// that are not adjacent, or carry controls, the same product is organised
+// by cosets: the amplitudes that differ only in the gate's target bits form
+// a 2^k-vector v, and the gate maps it to M v (Alg. 3's rep and j loops
+// enumerate these cosets for adjacent targets).  One lane owns whole cosets,
+// so the product runs in place, reads and writes each amplitude once
+// (2 N s bytes per gate, the minimum for a gate application) and needs no
+// expanded diagonals and no scratch vector.  Diagonal gates are applied
+// element-wise.  Diagonal gates folded in by the fusion planner multiply
+// the output rows.
+#include "internal.hpp"
+
+namespace diaq {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kCosetsPerLane = 2;
+
+template <typename R>
+struct Vec;
+template <>
+struct Vec<double> {
+  using V = double2;
+};
+template <>
+struct Vec<float> {
+  using V = float2;
+};
+
+struct KronArgs {
+  int64_t ncos;        // N >> k
+  int64_t off[8];      // scatter(r): amplitude offset of local index r
+  int32_t k;
+  int32_t sorted[3];   // target qubits ascending (zero-bit insertion)
+  uint64_t cmask;
+  int32_t adjoint;
+  int32_t nf;
+  const DiagFactor* factors;
+  double m[8][8][2];
+  double g[8][8][2];   // generator (adjoint step with a dot)
+};
+
+__device__ __forceinline__ int64_t insert_zeros(int64_t v, const KronArgs& a) {
+  for (int j = 0; j < a.k; j++) {
+    const int p = a.sorted[j];
+    v = (v & ((int64_t(1) << p) - 1)) | ((v >> p) << (p + 1));
+  }
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ void mat_vec(const KronArgs& a, const double (&xr)[1 << K], const double (&xi)[1 << K],
+                                        double (&yr)[1 << K], double (&yi)[1 << K]) {
+  constexpr int d = 1 << K;
+#pragma unroll
+  for (int r = 0; r < d; r++) {
+    double sr = 0, si = 0;
+#pragma unroll
+    for (int c = 0; c < d; c++) {
+      const double mr = a.adjoint ? a.m[c][r][0] : a.m[r][c][0];
+      const double mi = a.adjoint ? -a.m[c][r][1] : a.m[r][c][1];
+      sr += mr * xr[c] - mi * xi[c];
+      si += mr * xi[c] + mi * xr[c];
+    }
+    yr[r] = sr;
+    yi[r] = si;
+  }
+}
+
+__device__ __forceinline__ void apply_factors(const KronArgs& a, int64_t i, double& vr, double& vi) {
+  for (int f = 0; f < a.nf; f++) {
+    const DiagFactor& fa = a.factors[f];
+    int r = 0;
+    for (int b = 0; b < fa.k; b++) r |= int((i >> fa.q[b]) & 1) << b;
+    const double fr = fa.v[r][0], fi = fa.v[r][1];
+    const double nr = vr * fr - vi * fi;
+    vi = vr * fi + vi * fr;
+    vr = nr;
+  }
+}
+
+// In place: v <- (M or M^dagger) v on every coset whose controls are 1,
+// then the folded diagonal factors.
+template <typename R, int K>
+__global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename Vec<R>::V* __restrict__ v) {
+  using V = typename Vec<R>::V;
+  constexpr int d = 1 << K;
+  const int64_t c0 = int64_t(blockIdx.x) * (kBlock * kCosetsPerLane) + threadIdx.x;
+  int64_t base[kCosetsPerLane];
+  bool ok[kCosetsPerLane];
+  double xr[kCosetsPerLane][d], xi[kCosetsPerLane][d];
+#pragma unroll
+  for (int u = 0; u < kCosetsPerLane; u++) {
+    const int64_t cb = c0 + u * kBlock;
+    ok[u] = cb < a.ncos;
+    base[u] = ok[u] ? insert_zeros(cb, a) : 0;
+    ok[u] = ok[u] && ((uint64_t(base[u]) & a.cmask) == a.cmask);
+#pragma unroll
+    for (int r = 0; r < d; r++) {
+      V t = ok[u] ? v[base[u] + a.off[r]] : V{0, 0};
+      xr[u][r] = double(t.x);
+      xi[u][r] = double(t.y);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kCosetsPerLane; u++) {
+    if (!ok[u]) continue;
+    double yr[d], yi[d];
+    mat_vec<K>(a, xr[u], xi[u], yr, yi);
+#pragma unroll
+    for (int r = 0; r < d; r++) {
+      if (a.nf) apply_factors(a, base[u] + a.off[r], yr[r], yi[r]);
+      v[base[u] + a.off[r]] = V{R(yr[r]), R(yi[r])};
+    }
+  }
+  // rows whose controls are 0 keep their amplitude, but folded factors
+  // still multiply them
+  if (a.nf && a.cmask) {
+#pragma unroll
+    for (int u = 0; u < kCosetsPerLane; u++) {
+      const int64_t cb = c0 + u * kBlock;
+      if (cb >= a.ncos) continue;
+      const int64_t b = insert_zeros(cb, a);
+      if ((uint64_t(b) & a.cmask) == a.cmask) continue;
+#pragma unroll
+      for (int r = 0; r < d; r++) {
+        V t = v[b + a.off[r]];
+        double tr = double(t.x), ti = double(t.y);
+        apply_factors(a, b + a.off[r], tr, ti);
+        v[b + a.off[r]] = V{R(tr), R(ti)};
+      }
+    }
+  }
+}
+
+// Diagonal gates: element-wise phase, in place.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N, typename Vec<R>::V* __restrict__ v) {
+  using V = typename Vec<R>::V;
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
+    V t = v[i];
+    double tr = double(t.x), ti = double(t.y);
+    if ((uint64_t(i) & a.cmask) == a.cmask) {
+      int r = 0;
+      for (int j = 0; j < a.k; j++)
+        if ((i & a.off[1 << j]) != 0) r |= 1 << j;
+      const double mr = a.m[r][r][0], mi = a.adjoint ? -a.m[r][r][1] : a.m[r][r][1];
+      const double nr = mr * tr - mi * ti;
+      ti = mr * ti + mi * tr;
+      tr = nr;
+    }
+    if (a.nf) apply_factors(a, i, tr, ti);
+    v[i] = V{R(tr), R(ti)};
+  }
+}
+
+// Adjoint step: per coset, the generator dot conj(lam) (G psi) on the
+// current vectors (GEN), then psi <- U^dagger psi and lam <- U^dagger lam.
+// One partial sum per workgroup.
+template <typename R, int K, bool GEN>
+__global__ __launch_bounds__(kBlock) void kron_adjoint_kernel(KronArgs a, typename Vec<R>::V* __restrict__ psi,
+                                                              typename Vec<R>::V* __restrict__ lam,
+                                                              double2* __restrict__ partial, int32_t step_back) {
+  using V = typename Vec<R>::V;
+  constexpr int d = 1 << K;
+  double dre = 0, dim = 0;
+  const int64_t c0 = int64_t(blockIdx.x) * (kBlock * kCosetsPerLane) + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kCosetsPerLane; u++) {
+    const int64_t cb = c0 + u * kBlock;
+    if (cb >= a.ncos) continue;
+    const int64_t b = insert_zeros(cb, a);
+    if ((uint64_t(b) & a.cmask) != a.cmask) continue;
+    double pr[d], pi[d], lr[d], li[d];
+#pragma unroll
+    for (int r = 0; r < d; r++) {
+      const V p = psi[b + a.off[r]];
+      const V l = lam[b + a.off[r]];
+      pr[r] = double(p.x);
+      pi[r] = double(p.y);
+      lr[r] = double(l.x);
+      li[r] = double(l.y);
+    }
+    if (GEN) {
+#pragma unroll
+      for (int r = 0; r < d; r++) {
+        double gr = 0, gi = 0;
+#pragma unroll
+        for (int c = 0; c < d; c++) {
+          gr += a.g[r][c][0] * pr[c] - a.g[r][c][1] * pi[c];
+          gi += a.g[r][c][0] * pi[c] + a.g[r][c][1] * pr[c];
+        }
+        dre += lr[r] * gr + li[r] * gi;
+        dim += lr[r] * gi - li[r] * gr;
+      }
+    }
+    if (step_back) {
+      double yr[d], yi[d];
+      mat_vec<K>(a, pr, pi, yr, yi);
+#pragma unroll
+      for (int r = 0; r < d; r++) psi[b + a.off[r]] = V{R(yr[r]), R(yi[r])};
+      mat_vec<K>(a, lr, li, yr, yi);
+#pragma unroll
+      for (int r = 0; r < d; r++) lam[b + a.off[r]] = V{R(yr[r]), R(yi[r])};
+    }
+  }
+  if (GEN) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      dre += __shfl_xor(dre, off, 64);
+      dim += __shfl_xor(dim, off, 64);
+    }
+    __shared__ double2 wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wsum[wave] = double2{dre, dim};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double2 t = wsum[0];
+      for (int w = 1; w < kBlock / 64; w++) {
+        t.x += wsum[w].x;
+        t.y += wsum[w].y;
+      }
+      partial[blockIdx.x] = t;
+    }
+  }
+}
+
+KronArgs make_args(const LocalGate& lg, int n, bool adjoint, const DiagFactor* factors, int nf) {
+  KronArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.k = lg.k;
+  a.ncos = (int64_t(1) << n) >> lg.k;
+  for (int r = 0; r < (1 << lg.k); r++) {
+    int64_t o = 0;
+    for (int j = 0; j < lg.k; j++)
+      if ((r >> j) & 1) o |= int64_t(1) << lg.targets[j];
+    a.off[r] = o;
+  }
+  int st[3] = {lg.targets[0], lg.targets[1], lg.targets[2]};
+  std::sort(st, st + lg.k);
+  for (int j = 0; j < lg.k; j++) a.sorted[j] = st[j];
+  a.cmask = lg.cmask;
+  a.adjoint = adjoint ? 1 : 0;
+  a.factors = factors;
+  a.nf = factors ? nf : 0;
+  std::memcpy(a.m, lg.m, sizeof(a.m));
+  return a;
+}
+
+bool is_diagonal_local(const LocalGate& lg) {
+  const int d = 1 << lg.k;
+  for (int r = 0; r < d; r++)
+    for (int c = 0; c < d; c++)
+      if (r != c && lg.structural[r][c]) return false;
+  return true;
+}
+
+}  // namespace
+
+diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
+                                void* v, bool adjoint, const DiagFactor* factors, int nf) {
+  const KronArgs a = make_args(lg, n, adjoint, factors, nf);
+  const int64_t N = int64_t(1) << n;
+  if (is_diagonal_local(lg)) {
+    const int64_t blocks = std::min<int64_t>((N + kBlock - 1) / kBlock, int64_t(ctx->num_cus) * 32);
+    if (dt == DIAQ_C128)
+      hipLaunchKernelGGL(kron_diag_kernel<double>, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, a, N,
+                         static_cast<double2*>(v));
+    else
+      hipLaunchKernelGGL(kron_diag_kernel<float>, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, a, N,
+                         static_cast<float2*>(v));
+  } else {
+    const int64_t blocks = (a.ncos + kBlock * kCosetsPerLane - 1) / (kBlock * kCosetsPerLane);
+    const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
+#define DIAQ_KRON(R, K, PTR) hipLaunchKernelGGL((kron_apply_kernel<R, K>), grid, block, 0, stream, a, static_cast<PTR*>(v))
+    if (dt == DIAQ_C128) {
+      if (lg.k == 1) DIAQ_KRON(double, 1, double2);
+      else if (lg.k == 2) DIAQ_KRON(double, 2, double2);
+      else DIAQ_KRON(double, 3, double2);
+    } else {
+      if (lg.k == 1) DIAQ_KRON(float, 1, float2);
+      else if (lg.k == 2) DIAQ_KRON(float, 2, float2);
+      else DIAQ_KRON(float, 3, float2);
+    }
+#undef DIAQ_KRON
+  }
+  DIAQ_HIP(hipGetLastError());
+  return DIAQ_OK;
+}
+
+int64_t kron_adjoint_blocks(const LocalGate& lg, int n) {
+  const int64_t ncos = (int64_t(1) << n) >> lg.k;
+  return (ncos + kBlock * kCosetsPerLane - 1) / (kBlock * kCosetsPerLane);
+}
+
+diaq_status_t launch_kron_adjoint(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, const LocalGate* gen, int n,
+                                  diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back) {
+  (void)ctx;
+  KronArgs a = make_args(lg, n, true, nullptr, 0);
+  if (gen) std::memcpy(a.g, gen->m, sizeof(a.g));
+  const int64_t blocks = kron_adjoint_blocks(lg, n);
+  const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
+  const int sb = step_back ? 1 : 0;
+#define DIAQ_KADJ(R, K, G, PTR)                                                                           \
+  hipLaunchKernelGGL((kron_adjoint_kernel<R, K, G>), grid, block, 0, stream, a, static_cast<PTR*>(psi), \
+                     static_cast<PTR*>(lam), partial, sb)
+  if (dt == DIAQ_C128) {
+    if (gen) {
+      if (lg.k == 1) DIAQ_KADJ(double, 1, true, double2);
+      else if (lg.k == 2) DIAQ_KADJ(double, 2, true, double2);
+      else DIAQ_KADJ(double, 3, true, double2);
+    } else {
+      if (lg.k == 1) DIAQ_KADJ(double, 1, false, double2);
+      else if (lg.k == 2) DIAQ_KADJ(double, 2, false, double2);
+      else DIAQ_KADJ(double, 3, false, double2);
+    }
+  } else {
+    if (gen) {
+      if (lg.k == 1) DIAQ_KADJ(float, 1, true, float2);
+      else if (lg.k == 2) DIAQ_KADJ(float, 2, true, float2);
+      else DIAQ_KADJ(float, 3, true, float2);
+    } else {
+      if (lg.k == 1) DIAQ_KADJ(float, 1, false, float2);
+      else if (lg.k == 2) DIAQ_KADJ(float, 2, false, float2);
+      else DIAQ_KADJ(float, 3, false, float2);
+    }
+  }
+#undef DIAQ_KADJ
+  DIAQ_HIP(hipGetLastError());
+  return DIAQ_OK;
+}
+
+}  // namespace diaq

@@ -153,7 +153,7 @@ bool diagonal_factor(const diaq_gate_t* g, const LocalGate& lg, DiagFactor* f) {
 }  // namespace
 
 diaq_status_t plan_fusion(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, diaq_dtype_t dt,
-                          std::vector<FusedOp>* ops) {
+                          std::vector<FusedOp>* ops, bool kron) {
   if (kmax < 1 || kmax > 3) return fail(DIAQ_ERR_INVALID_ARGUMENT, "max_fused_qubits must be 1..3");
   const double s = double(elem_bytes(dt));
   ops->clear();
@@ -192,7 +192,7 @@ diaq_status_t plan_fusion(const diaq_gate_t* gates, int64_t ngates, int n, int k
         embed(lg, U, u, B);
         local_product(1 << u, A, B, Cm);
         const LocalGate fused = to_local_gate(U, u, Cm);
-        if (op_bytes(fused, n, s) <= op_bytes(X.core, n, s) + op_bytes(lg, n, s)) {
+        if (kron || op_bytes(fused, n, s) <= op_bytes(X.core, n, s) + op_bytes(lg, n, s)) {
           X.core = fused;
           X.ngates++;
           continue;

@@ -533,11 +533,15 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
   return launch_typed<float>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
 }
 
-static diaq_status_t final_reduce(diaq_ctx* ctx, const double2* partial, int64_t count, double* dres) {
-  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(1024), 0, ctx->stream, partial, count,
+diaq_status_t launch_final_reduce(hipStream_t stream, const double2* partial, int64_t count, double* dres) {
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(1024), 0, stream, partial, count,
                      reinterpret_cast<double2*>(dres));
   DIAQ_HIP(hipGetLastError());
   return DIAQ_OK;
+}
+
+static diaq_status_t final_reduce(diaq_ctx* ctx, const double2* partial, int64_t count, double* dres) {
+  return launch_final_reduce(ctx->stream, partial, count, dres);
 }
 
 diaq_status_t launch_expect(diaq_ctx* ctx, const SpmvOp& op, const void* psi, const void* phi, double* dres) {

@@ -97,7 +97,7 @@ _SIGS = {
                            ctypes.POINTER(diaq_plan_t)],
     "diaq_expect": [_P, _P, _P, _P, ctypes.POINTER(_D)],
     "diaq_adjoint_grad": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _P, _P, _P, _I64,
-                          ctypes.POINTER(_D), ctypes.POINTER(_D)],
+                          ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(diaq_plan_t)],
     "diaq_set_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
     "diaq_get_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
     "diaq_plan_count": [ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, ctypes.POINTER(diaq_plan_t),
@@ -430,7 +430,7 @@ def expect(H: DiaqMatrix, psi: torch.Tensor, phi: torch.Tensor | None = None) ->
 
 
 def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: int,
-                 work: torch.Tensor | None = None):
+                 work: torch.Tensor | None = None, plan: diaq_plan_t | None = None):
     """(E, dE/dtheta) by the adjoint reverse sweep; synchronises."""
     n, _, dt, _, _ = H.info()
     if work is None:
@@ -442,7 +442,8 @@ def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: in
     grad = np.zeros(max(nparams, 1), dtype=np.float64)
     _check(load().diaq_adjoint_grad(H.ctx.handle, arr, len(gates), n, dt, H.handle, _vec(psi0, n, dt, "psi0"),
                                     _P(work.data_ptr()), nparams, ctypes.byref(e),
-                                    grad.ctypes.data_as(ctypes.POINTER(_D))))
+                                    grad.ctypes.data_as(ctypes.POINTER(_D)),
+                                    ctypes.byref(plan) if plan is not None else None))
     return e.value, grad[:nparams]
 
 

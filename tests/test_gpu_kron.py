@@ -1,0 +1,99 @@
+"""GPU parity of the Alg. 3 path (plan.kron: gates applied in place
+without expanded diagonals), alone and with fusion, and of the adjoint
+gradient on that path."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2405_01250_amd import diaq as D
+from paper_2405_01250_amd import inputs as W
+from tests.gpu_util import assert_state_close, to_dev, to_host
+from tests.test_gpu_kernels import _random_gate
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.mark.parametrize("fuse", [False, True])
+@pytest.mark.parametrize("seed", range(6))
+def test_kron_random_circuits(fuse, seed):
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(1, 15))
+    gates = [_random_gate(rng, n) for _ in range(int(rng.integers(1, 50)))]
+    x = W.random_state(n, seed)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi, plan=D.make_plan(kron=True, fuse=fuse, max_fused_qubits=3))
+    assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "kron fuse=%s seed %d" % (fuse, seed))
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3])
+def test_kron_workloads(kmax):
+    for name, n, gates, x in [("qft", 16, W.qft(16), W.random_state(16, 2)),
+                              ("random_layered", 16, W.random_layered(16, 4, 9), W.zero_state(16)),
+                              ("tfim", 14, W.tfim(14, 6), W.random_state(14, 5)),
+                              ("hea", 12, W.hea(12, 2, 6)[0], W.zero_state(12))]:
+        for fuse in (False, True):
+            psi = to_dev(x)
+            D.apply_circuit(gates, psi, plan=D.make_plan(kron=True, fuse=fuse, max_fused_qubits=kmax))
+            assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "%s k=%d fuse=%s" % (name, kmax, fuse))
+
+
+def test_kron_complex64_and_large_n():
+    n = 22
+    gates = W.random_layered(n, 1, 22)
+    x = W.zero_state(n)
+    ref = orc.apply_circuit(x, n, gates)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi, plan=D.make_plan(kron=True))
+    assert_state_close(to_host(psi), ref, TOL64, "kron n=22")
+    psi32 = to_dev(x, torch.complex64)
+    D.apply_circuit(gates, psi32, plan=D.make_plan(kron=True, fuse=True, max_fused_qubits=3))
+    assert_state_close(to_host(psi32), ref, TOL32, "kron c64 n=22", l2tol=1e-4)
+
+
+def test_kron_matches_plain_path_bitwise_structure():
+    # same circuit, both paths, agree to rounding
+    n = 18
+    gates = W.qft(n)
+    x = to_dev(W.random_state(n, 18))
+    a, b = x.clone(), x.clone()
+    D.apply_circuit(gates, a)
+    D.apply_circuit(gates, b, plan=D.make_plan(kron=True, fuse=True))
+    assert_state_close(to_host(a), to_host(b), TOL64, "plain vs kron")
+
+
+@pytest.mark.parametrize("n,layers", [(6, 2), (12, 3)])
+def test_kron_adjoint(n, layers):
+    gates, theta, terms = W.hea(n, layers, 40 + n)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = W.zero_state(n)
+    e, g = D.adjoint_grad(gates, H, to_dev(psi0), len(theta), plan=D.make_plan(kron=True))
+    assert abs(e - orc.energy(psi0, n, gates, terms)) <= 1e-12
+    ps = orc.param_shift_grad(psi0, n, gates, terms, len(theta))
+    assert np.linalg.norm(g - ps) <= 1e-10 * max(1.0, np.linalg.norm(ps))
+
+
+def test_kron_adjoint_controlled_and_two_qubit_rotations():
+    rng = np.random.default_rng(5)
+    n = 7
+    gates, pidx = [], 0
+    for kind, nt, nc in [("RX", 1, 0), ("RYY", 2, 0), ("RZZ", 2, 0), ("RY", 1, 1), ("P", 1, 2), ("RXX", 2, 1)]:
+        qs = [int(q) for q in rng.permutation(n)]
+        gates.append(W.u3(*rng.uniform(0, 6, 3), qs[-1]))
+        gates.append(W.Gate(kind, tuple(qs[:nt]), tuple(qs[nt:nt + nc]), (float(rng.uniform(0, 6)),), pidx, 1.3))
+        pidx += 1
+    terms = [(int(rng.integers(0, 1 << n)), int(rng.integers(0, 1 << n)), float(rng.standard_normal()))
+             for _ in range(6)]
+    H = D.from_pauli_sum(n, terms)
+    psi0 = W.random_state(n, 8)
+    e, g = D.adjoint_grad(gates, H, to_dev(psi0), pidx, plan=D.make_plan(kron=True))
+    e2, g2 = D.adjoint_grad(gates, H, to_dev(psi0), pidx)
+    assert abs(e - orc.energy(psi0, n, gates, terms)) <= 1e-12
+    fd = orc.fd_grad(psi0, n, gates, terms, pidx, h=1e-4)
+    assert np.max(np.abs(g - fd)) <= 1e-7 * max(1.0, np.max(np.abs(fd)))
+    assert np.max(np.abs(g - g2)) <= 1e-12
