@@ -317,6 +317,80 @@ __global__ void batch_reset_kernel(int32_t* queue, double* expvals, int64_t nc, 
   if (i < nc) expvals[i] = 0.0;
   if (i < ng) grads[i] = 0.0;
 }
+// ---------------------------------------------------------------------------
+// Wide circuits: every gate is a grid-wide Alg. 3 launch (in place), issued
+// on side streams so several circuits are in flight at once.
+// ---------------------------------------------------------------------------
+
+constexpr int kWideMinQubits = 15;
+constexpr int kWideStreams = 4;
+constexpr int kObsBlock = 256;
+
+__global__ void wide_init_kernel(double2* psi, int64_t N) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride)
+    psi[i] = double2{i == 0 ? 1.0 : 0.0, 0.0};
+}
+
+// lambda = H psi for the diagonal observable; one partial <psi|lambda> per
+// workgroup.
+__global__ __launch_bounds__(kObsBlock) void wide_observable_kernel(const double2* __restrict__ psi,
+                                                                    double2* __restrict__ lam, int64_t N,
+                                                                    const uint64_t* __restrict__ zm,
+                                                                    const double* __restrict__ coef, int nt,
+                                                                    double2* __restrict__ partial) {
+  double re = 0, im = 0;
+  const int64_t i = int64_t(blockIdx.x) * kObsBlock + threadIdx.x;
+  if (i < N) {
+    double h = 0;
+    for (int t = 0; t < nt; t++) h += (__popcll(uint64_t(i) & zm[t]) & 1) ? -coef[t] : coef[t];
+    const double2 p = psi[i];
+    const double2 l{h * p.x, h * p.y};
+    lam[i] = l;
+    re = p.x * l.x + p.y * l.y;
+    im = p.x * l.y - p.y * l.x;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  __shared__ double2 wsum[kObsBlock / 64];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = double2{re, im};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 t = wsum[0];
+    for (int w = 1; w < kObsBlock / 64; w++) {
+      t.x += wsum[w].x;
+      t.y += wsum[w].y;
+    }
+    partial[blockIdx.x] = t;
+  }
+}
+
+struct WideRes {
+  int32_t circ;
+  int32_t ndots;
+  int64_t dot0;  // first slot in the dot table
+  int64_t p0;    // first gradient slot of the circuit
+};
+
+struct WideDot {
+  int32_t pidx;
+  int32_t pad;
+  double scale;
+};
+
+// One lane per wide circuit: expectation value and gradient sums in a fixed
+// (reverse-sweep) order.
+__global__ void wide_finalize_kernel(const WideRes* __restrict__ res, int nwide, const WideDot* __restrict__ meta,
+                                     const double2* __restrict__ dots, const double2* __restrict__ evals,
+                                     double* __restrict__ expvals, double* __restrict__ grads) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwide) return;
+  const WideRes r = res[w];
+  expvals[r.circ] = evals[w].x;
+  for (int j = 0; j < r.ndots; j++) grads[r.p0 + meta[r.dot0 + j].pidx] += meta[r.dot0 + j].scale * dots[r.dot0 + j].y;
+}
 
 int rot_of(int kind) {
   switch (kind) {
@@ -331,18 +405,39 @@ int rot_of(int kind) {
   }
 }
 
+struct WideCirc {
+  int32_t c = 0, n = 0, slot = 0;
+  int64_t g0 = 0;    // first gate in the batch gate table
+  int64_t s0 = 0;    // workspace offset of psi (lambda follows)
+  int64_t t0 = 0;    // first observable term
+  int32_t nt = 0;
+  int64_t dot0 = 0;  // first dot slot
+  std::vector<LocalGate> lg, gen;
+  std::vector<int32_t> pidx, rot;
+};
+
 }  // namespace
 }  // namespace diaq
 
 struct diaq_batch {
   diaq_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
+  hipStream_t side[diaq::kWideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[diaq::kWideStreams] = {};
   int32_t ncirc = 0;
+  int32_t nnarrow = 0;
   int64_t nparams = 0;
   int64_t ngates = 0;
-  void* dmem = nullptr;          // circuits, gates, terms, order, theta, results, queue
-  double2* ws = nullptr;         // per-circuit vectors
+  void* dmem = nullptr;          // tables, results, queue, partials
+  double2* ws = nullptr;         // per-circuit vectors outside LDS
   diaq::BatchArgs args{};
+  std::vector<diaq::WideCirc> wide;
+  diaq::WideRes* d_wres = nullptr;
+  diaq::WideDot* d_wmeta = nullptr;
+  double2* d_dots = nullptr;
+  double2* d_evals = nullptr;
+  double2* d_partial[diaq::kWideStreams] = {};
   double* pinned = nullptr;      // theta in, expvals + grads out
   int64_t pinned_theta = 0, pinned_out = 0;
   size_t lds_bytes = 0;
@@ -355,6 +450,40 @@ struct diaq_batch {
 
 namespace diaq {
 namespace {
+
+diaq_status_t enqueue_wide(diaq_batch* b, const WideCirc& w, hipStream_t s, bool use_theta) {
+  diaq_ctx* ctx = b->ctx;
+  const int64_t N = int64_t(1) << w.n;
+  double2* psi = b->ws + w.s0;
+  double2* lam = psi + N;
+  double2* part = b->d_partial[w.slot];
+  const int64_t ib = std::min<int64_t>((N + 255) / 256, int64_t(ctx->num_cus) * 16);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(unsigned(ib)), dim3(256), 0, s, psi, N);
+  DIAQ_HIP(hipGetLastError());
+  auto dmat = [&](size_t j) -> const double* {
+    return (use_theta && w.pidx[j] >= 0 && w.rot[j] != kFixed) ? b->args.mats + (w.g0 + int64_t(j)) * 32 : nullptr;
+  };
+  for (size_t j = 0; j < w.lg.size(); j++)
+    DIAQ_TRY(launch_kron_apply(ctx, s, w.lg[j], w.n, DIAQ_C128, psi, false, nullptr, 0, dmat(j)));
+  const int64_t ob = (N + kObsBlock - 1) / kObsBlock;
+  hipLaunchKernelGGL(wide_observable_kernel, dim3(unsigned(ob)), dim3(kObsBlock), 0, s, psi, lam, N,
+                     b->args.zmask + w.t0, b->args.coef + w.t0, w.nt, part);
+  DIAQ_HIP(hipGetLastError());
+  const int64_t wi = &w - b->wide.data();
+  DIAQ_TRY(launch_final_reduce(s, part, ob, reinterpret_cast<double*>(b->d_evals + wi)));
+  int64_t slot = w.dot0;
+  for (int64_t j = int64_t(w.lg.size()) - 1; j >= 0; j--) {
+    const bool diff = w.pidx[j] >= 0;
+    if (!diff && j == 0) break;
+    DIAQ_TRY(launch_kron_adjoint(ctx, s, w.lg[j], diff ? &w.gen[j] : nullptr, w.n, DIAQ_C128, psi, lam, part, j > 0,
+                                 dmat(size_t(j))));
+    if (diff) {
+      DIAQ_TRY(launch_final_reduce(s, part, kron_adjoint_blocks(w.lg[j], w.n), reinterpret_cast<double*>(b->d_dots + slot)));
+      slot++;
+    }
+  }
+  return DIAQ_OK;
+}
 
 diaq_status_t enqueue(diaq_batch* b, bool use_theta) {
   BatchArgs args = b->args;
@@ -371,8 +500,26 @@ diaq_status_t enqueue(diaq_batch* b, bool use_theta) {
   hipLaunchKernelGGL(batch_reset_kernel, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, b->stream, args.queue,
                      args.expvals, int64_t(b->ncirc), args.grads, b->nparams);
   DIAQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(batch_kernel, dim3(unsigned(b->grid)), dim3(kThreads), b->lds_bytes, b->stream, args);
-  DIAQ_HIP(hipGetLastError());
+  const bool wide = !b->wide.empty();
+  if (wide) {
+    DIAQ_HIP(hipEventRecord(b->fork, b->stream));
+    for (int j = 0; j < kWideStreams; j++) DIAQ_HIP(hipStreamWaitEvent(b->side[j], b->fork, 0));
+  }
+  if (b->nnarrow) {
+    hipLaunchKernelGGL(batch_kernel, dim3(unsigned(b->grid)), dim3(kThreads), b->lds_bytes, b->stream, args);
+    DIAQ_HIP(hipGetLastError());
+  }
+  if (wide) {
+    for (const auto& w : b->wide) DIAQ_TRY(enqueue_wide(b, w, b->side[w.slot], use_theta));
+    for (int j = 0; j < kWideStreams; j++) {
+      DIAQ_HIP(hipEventRecord(b->join[j], b->side[j]));
+      DIAQ_HIP(hipStreamWaitEvent(b->stream, b->join[j], 0));
+    }
+    const int nw = int(b->wide.size());
+    hipLaunchKernelGGL(wide_finalize_kernel, dim3(unsigned((nw + 63) / 64)), dim3(64), 0, b->stream, b->d_wres, nw,
+                       b->d_wmeta, b->d_dots, b->d_evals, args.expvals, args.grads);
+    DIAQ_HIP(hipGetLastError());
+  }
   double* out = b->pinned + b->pinned_theta;
   DIAQ_HIP(hipMemcpyAsync(out, args.expvals, size_t(b->ncirc) * sizeof(double), hipMemcpyDeviceToHost, b->stream));
   if (b->nparams)
@@ -391,11 +538,18 @@ extern "C" {
 diaq_status_t diaq_batch_free(diaq_batch_t b) {
   if (!b) return DIAQ_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (int j = 0; j < kWideStreams; j++)
+    if (b->side[j]) (void)hipStreamSynchronize(b->side[j]);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->g) (void)hipGraphDestroy(b->g);
   if (b->dmem) (void)hipFree(b->dmem);
   if (b->ws) (void)hipFree(b->ws);
   if (b->pinned) (void)hipHostFree(b->pinned);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (int j = 0; j < kWideStreams; j++) {
+    if (b->join[j]) (void)hipEventDestroy(b->join[j]);
+    if (b->side[j]) (void)hipStreamDestroy(b->side[j]);
+  }
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return DIAQ_OK;
@@ -411,14 +565,19 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     std::vector<BGate> gates;
     std::vector<uint64_t> zm;
     std::vector<double> coef;
+    std::vector<WideCirc> wide;
+    std::vector<WideRes> wres;
+    std::vector<WideDot> wmeta;
     int64_t nparams = 0, ws_elems = 0;
     std::vector<double> work(static_cast<size_t>(ncircuits));
+    std::vector<int32_t> narrow;
     for (int c = 0; c < ncircuits; c++) {
       const diaq_circuit_t& C = circuits[c];
       if (C.nqubits < 1 || C.nqubits > 30) return fail(DIAQ_ERR_INVALID_ARGUMENT, "circuit %d: nqubits %d", c, C.nqubits);
       if (C.ngates < 0 || (C.ngates > 0 && !C.gates) || C.nparams < 0 || C.nterms < 0 ||
           (C.nterms > 0 && (!C.zmask || !C.coef)))
         return fail(DIAQ_ERR_INVALID_ARGUMENT, "circuit %d: bad arrays", c);
+      const bool is_wide = C.nqubits >= kWideMinQubits;
       BCirc& bc = circ[c];
       bc.n = C.nqubits;
       bc.nparams = C.nparams;
@@ -435,6 +594,15 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
         if (C.zmask[t] >> C.nqubits) return fail(DIAQ_ERR_INVALID_ARGUMENT, "circuit %d: term %d outside register", c, t);
         zm.push_back(C.zmask[t]);
         coef.push_back(C.coef[t]);
+      }
+      WideCirc wc;
+      if (is_wide) {
+        wc.c = c;
+        wc.n = C.nqubits;
+        wc.g0 = bc.g0;
+        wc.s0 = bc.s0;
+        wc.t0 = bc.t0;
+        wc.nt = bc.nt;
       }
       for (int64_t gi = 0; gi < C.ngates; gi++) {
         const diaq_gate_t* g = &C.gates[gi];
@@ -461,10 +629,10 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
         bg.diag = diag ? 1 : 0;
         bg.rot = rot_of(g->kind);
         bg.pidx = -1;
+        LocalGate gen = lg;
         if (g->param_index >= 0) {
           if (g->param_index >= C.nparams)
             return fail(DIAQ_ERR_INVALID_ARGUMENT, "circuit %d gate %lld: param_index out of range", c, (long long)gi);
-          LocalGate gen = lg;
           if (!local_generator(g, &gen))
             return fail(DIAQ_ERR_UNSUPPORTED, "circuit %d gate %lld: not a rotation", c, (long long)gi);
           for (int r = 0; r < d; r++)
@@ -477,16 +645,56 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
           bg.p0 = bc.p0;
         }
         gates.push_back(bg);
+        if (is_wide) {
+          wc.lg.push_back(lg);
+          wc.gen.push_back(gen);
+          wc.pidx.push_back(bg.pidx);
+          wc.rot.push_back(bg.rot);
+        }
       }
       work[c] = double(int64_t(1) << C.nqubits) * double(3 * C.ngates + 1);
+      if (is_wide) {
+        WideRes r;
+        r.circ = c;
+        r.dot0 = int64_t(wmeta.size());
+        r.p0 = bc.p0;
+        wc.dot0 = r.dot0;
+        // dot slots in reverse-sweep order
+        for (int64_t gi = C.ngates - 1; gi >= 0; gi--)
+          if (wc.pidx[size_t(gi)] >= 0) wmeta.push_back(WideDot{wc.pidx[size_t(gi)], 0, C.gates[gi].param_scale});
+        r.ndots = int32_t(int64_t(wmeta.size()) - r.dot0);
+        wres.push_back(r);
+        wide.push_back(std::move(wc));
+      } else {
+        narrow.push_back(c);
+      }
     }
-    std::vector<int32_t> order(static_cast<size_t>(ncircuits));
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+    // narrow circuits: queue order, largest work first; wide circuits:
+    // greedy assignment of the largest to the least-loaded side stream
+    std::stable_sort(narrow.begin(), narrow.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+    {
+      std::vector<size_t> idx(wide.size());
+      std::iota(idx.begin(), idx.end(), 0);
+      std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return work[wide[x].c] > work[wide[y].c]; });
+      double load[kWideStreams] = {0, 0, 0, 0};
+      for (size_t x : idx) {
+        int best = 0;
+        for (int j = 1; j < kWideStreams; j++)
+          if (load[j] < load[best]) best = j;
+        wide[x].slot = best;
+        load[best] += work[wide[x].c];
+      }
+    }
+    int64_t maxpart = 1;
+    for (const auto& w : wide) {
+      maxpart = std::max<int64_t>(maxpart, ((int64_t(1) << w.n) + kObsBlock - 1) / kObsBlock);
+      for (const auto& lg : w.lg) maxpart = std::max<int64_t>(maxpart, kron_adjoint_blocks(lg, w.n));
+    }
 
     diaq_batch* b = new diaq_batch();
     b->ctx = ctx;
     b->ncirc = ncircuits;
+    b->nnarrow = int32_t(narrow.size());
     b->nparams = nparams;
     auto bail = [&](diaq_status_t st) {
       diaq_batch_free(b);
@@ -494,19 +702,31 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     };
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
       return bail(fail(DIAQ_ERR_DEVICE, "hipStreamCreate failed"));
-    // one device block: circuits | gates | zmask | coef | order | theta | expvals | grads | queue
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(DIAQ_ERR_DEVICE, "hipEventCreate failed"));
+    for (int j = 0; j < kWideStreams; j++) {
+      if (hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&b->join[j], hipEventDisableTiming) != hipSuccess)
+        return bail(fail(DIAQ_ERR_DEVICE, "side stream setup failed"));
+    }
+    // one device block for every table
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     size_t off = 0;
     const size_t o_circ = off; off += al(circ.size() * sizeof(BCirc) + 1);
     const size_t o_gates = off; off += al(gates.size() * sizeof(BGate) + 1);
     const size_t o_zm = off; off += al(zm.size() * sizeof(uint64_t) + 1);
     const size_t o_coef = off; off += al(coef.size() * sizeof(double) + 1);
-    const size_t o_order = off; off += al(order.size() * sizeof(int32_t) + 1);
+    const size_t o_order = off; off += al(narrow.size() * sizeof(int32_t) + 1);
     const size_t o_theta = off; off += al(size_t(nparams) * sizeof(double) + 1);
     const size_t o_mats = off; off += al(gates.size() * 32 * sizeof(double) + 1);
     const size_t o_exp = off; off += al(size_t(ncircuits) * sizeof(double) + 1);
     const size_t o_grad = off; off += al(size_t(nparams) * sizeof(double) + 1);
     const size_t o_queue = off; off += 256;
+    const size_t o_wres = off; off += al(wres.size() * sizeof(WideRes) + 1);
+    const size_t o_wmeta = off; off += al(wmeta.size() * sizeof(WideDot) + 1);
+    const size_t o_dots = off; off += al(wmeta.size() * sizeof(double2) + 1);
+    const size_t o_evals = off; off += al(wide.size() * sizeof(double2) + 1);
+    const size_t o_part = off; off += al(size_t(maxpart) * sizeof(double2)) * kWideStreams;
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
       (void)hipGetLastError();
       return bail(fail(DIAQ_ERR_OUT_OF_MEMORY, "batch tables: %zu bytes", off));
@@ -524,7 +744,9 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     up(o_gates, gates.data(), gates.size() * sizeof(BGate));
     up(o_zm, zm.data(), zm.size() * sizeof(uint64_t));
     up(o_coef, coef.data(), coef.size() * sizeof(double));
-    up(o_order, order.data(), order.size() * sizeof(int32_t));
+    up(o_order, narrow.data(), narrow.size() * sizeof(int32_t));
+    up(o_wres, wres.data(), wres.size() * sizeof(WideRes));
+    up(o_wmeta, wmeta.data(), wmeta.size() * sizeof(WideDot));
     if (e != hipSuccess) return bail(fail(DIAQ_ERR_DEVICE, "batch upload: %s", hipGetErrorString(e)));
     b->args.circ = reinterpret_cast<const BCirc*>(base + o_circ);
     b->args.gates = reinterpret_cast<const BGate*>(base + o_gates);
@@ -533,12 +755,19 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     b->args.order = reinterpret_cast<const int32_t*>(base + o_order);
     b->args.theta = reinterpret_cast<const double*>(base + o_theta);
     b->args.mats = reinterpret_cast<const double*>(base + o_mats);
-    b->ngates = int64_t(gates.size());
     b->args.expvals = reinterpret_cast<double*>(base + o_exp);
     b->args.grads = reinterpret_cast<double*>(base + o_grad);
     b->args.queue = reinterpret_cast<int32_t*>(base + o_queue);
     b->args.ws = b->ws;
-    b->args.ncirc = ncircuits;
+    b->args.ncirc = int32_t(narrow.size());
+    b->d_wres = reinterpret_cast<WideRes*>(base + o_wres);
+    b->d_wmeta = reinterpret_cast<WideDot*>(base + o_wmeta);
+    b->d_dots = reinterpret_cast<double2*>(base + o_dots);
+    b->d_evals = reinterpret_cast<double2*>(base + o_evals);
+    for (int j = 0; j < kWideStreams; j++)
+      b->d_partial[j] = reinterpret_cast<double2*>(base + o_part + size_t(j) * al(size_t(maxpart) * sizeof(double2)));
+    b->ngates = int64_t(gates.size());
+    b->wide = std::move(wide);
     b->pinned_theta = nparams;
     b->pinned_out = ncircuits + nparams;
     if (hipHostMalloc(reinterpret_cast<void**>(&b->pinned), size_t(b->pinned_theta + b->pinned_out + 1) * sizeof(double),
@@ -553,7 +782,7 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
       (void)hipGetLastError();
       return bail(fail(DIAQ_ERR_DEVICE, "cannot reserve %zu bytes of LDS per workgroup", b->lds_bytes));
     }
-    b->grid = std::max(1, std::min(ctx->num_cus, ncircuits));
+    b->grid = std::max(1, std::min(ctx->num_cus, b->nnarrow));
     b->graph = (flags & DIAQ_BATCH_GRAPH) != 0;
     *out = b;
     return DIAQ_OK;

@@ -205,15 +205,19 @@ diaq_status_t launch_generator_dot(diaq_ctx* ctx, const LocalGate& gen, int n,
                                    diaq_dtype_t dt, const void* lam,
                                    const void* psi, double* dres);
 
-// kron.hip: Alg. 3 products without expansion, in place on `v`.
+// kron.hip: Alg. 3 products without expansion, in place on `v`.  `dmat`
+// (device, 4 x 4 complex, at most 2 targets) replaces lg's matrix when the
+// matrix depends on angles that live on the device.
 diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
-                                void* v, bool adjoint, const DiagFactor* factors = nullptr, int nf = 0);
+                                void* v, bool adjoint, const DiagFactor* factors = nullptr, int nf = 0,
+                                const double* dmat = nullptr);
 // Reverse-sweep step: optional generator dot (one double2 partial per
 // workgroup into `partial`, kron_adjoint_blocks of them), then
 // psi, lam <- U^dagger psi, U^dagger lam when step_back.
 int64_t kron_adjoint_blocks(const LocalGate& lg, int n);
 diaq_status_t launch_kron_adjoint(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, const LocalGate* gen,
-                                  int n, diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back);
+                                  int n, diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back,
+                                  const double* dmat = nullptr);
 // spmv.hip: one workgroup sums partial[0..count) into dres (2 doubles).
 diaq_status_t launch_final_reduce(hipStream_t stream, const double2* partial, int64_t count, double* dres);
 

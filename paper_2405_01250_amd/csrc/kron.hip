@@ -40,9 +40,20 @@ struct KronArgs {
   int32_t adjoint;
   int32_t nf;
   const DiagFactor* factors;
+  const double* dmat;  // device 4 x 4 local matrix (k <= 2), replaces m
   double m[8][8][2];
   double g[8][8][2];   // generator (adjoint step with a dot)
 };
+
+// Local matrix element (r, c), part j: from the kernel arguments, or with DM
+// from device memory (matrices that depend on angles held on the device).
+template <bool DM>
+__device__ __forceinline__ double mel(const KronArgs& a, int r, int c, int j) {
+  if constexpr (DM)
+    return a.dmat[(r * 4 + c) * 2 + j];
+  else
+    return a.m[r][c][j];
+}
 
 __device__ __forceinline__ int64_t insert_zeros(int64_t v, const KronArgs& a) {
   for (int j = 0; j < a.k; j++) {
@@ -52,7 +63,7 @@ __device__ __forceinline__ int64_t insert_zeros(int64_t v, const KronArgs& a) {
   return v;
 }
 
-template <int K>
+template <int K, bool DM>
 __device__ __forceinline__ void mat_vec(const KronArgs& a, const double (&xr)[1 << K], const double (&xi)[1 << K],
                                         double (&yr)[1 << K], double (&yi)[1 << K]) {
   constexpr int d = 1 << K;
@@ -61,8 +72,8 @@ __device__ __forceinline__ void mat_vec(const KronArgs& a, const double (&xr)[1 
     double sr = 0, si = 0;
 #pragma unroll
     for (int c = 0; c < d; c++) {
-      const double mr = a.adjoint ? a.m[c][r][0] : a.m[r][c][0];
-      const double mi = a.adjoint ? -a.m[c][r][1] : a.m[r][c][1];
+      const double mr = a.adjoint ? mel<DM>(a, c, r, 0) : mel<DM>(a, r, c, 0);
+      const double mi = a.adjoint ? -mel<DM>(a, c, r, 1) : mel<DM>(a, r, c, 1);
       sr += mr * xr[c] - mi * xi[c];
       si += mr * xi[c] + mi * xr[c];
     }
@@ -85,7 +96,7 @@ __device__ __forceinline__ void apply_factors(const KronArgs& a, int64_t i, doub
 
 // In place: v <- (M or M^dagger) v on every coset whose controls are 1,
 // then the folded diagonal factors.
-template <typename R, int K>
+template <typename R, int K, bool DM>
 __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename Vec<R>::V* __restrict__ v) {
   using V = typename Vec<R>::V;
   constexpr int d = 1 << K;
@@ -110,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
   for (int u = 0; u < kCosetsPerLane; u++) {
     if (!ok[u]) continue;
     double yr[d], yi[d];
-    mat_vec<K>(a, xr[u], xi[u], yr, yi);
+    mat_vec<K, DM>(a, xr[u], xi[u], yr, yi);
 #pragma unroll
     for (int r = 0; r < d; r++) {
       if (a.nf) apply_factors(a, base[u] + a.off[r], yr[r], yi[r]);
@@ -138,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
 }
 
 // Diagonal gates: element-wise phase, in place.
-template <typename R>
+template <typename R, bool DM>
 __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N, typename Vec<R>::V* __restrict__ v) {
   using V = typename Vec<R>::V;
   const int64_t stride = int64_t(gridDim.x) * kBlock;
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
       int r = 0;
       for (int j = 0; j < a.k; j++)
         if ((i & a.off[1 << j]) != 0) r |= 1 << j;
-      const double mr = a.m[r][r][0], mi = a.adjoint ? -a.m[r][r][1] : a.m[r][r][1];
+      const double mr = mel<DM>(a, r, r, 0), mi = a.adjoint ? -mel<DM>(a, r, r, 1) : mel<DM>(a, r, r, 1);
       const double nr = mr * tr - mi * ti;
       ti = mr * ti + mi * tr;
       tr = nr;
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
 // Adjoint step: per coset, the generator dot conj(lam) (G psi) on the
 // current vectors (GEN), then psi <- U^dagger psi and lam <- U^dagger lam.
 // One partial sum per workgroup.
-template <typename R, int K, bool GEN>
+template <typename R, int K, bool GEN, bool DM>
 __global__ __launch_bounds__(kBlock) void kron_adjoint_kernel(KronArgs a, typename Vec<R>::V* __restrict__ psi,
                                                               typename Vec<R>::V* __restrict__ lam,
                                                               double2* __restrict__ partial, int32_t step_back) {
@@ -201,10 +212,10 @@ __global__ __launch_bounds__(kBlock) void kron_adjoint_kernel(KronArgs a, typena
     }
     if (step_back) {
       double yr[d], yi[d];
-      mat_vec<K>(a, pr, pi, yr, yi);
+      mat_vec<K, DM>(a, pr, pi, yr, yi);
 #pragma unroll
       for (int r = 0; r < d; r++) psi[b + a.off[r]] = V{R(yr[r]), R(yi[r])};
-      mat_vec<K>(a, lr, li, yr, yi);
+      mat_vec<K, DM>(a, lr, li, yr, yi);
 #pragma unroll
       for (int r = 0; r < d; r++) lam[b + a.off[r]] = V{R(yr[r]), R(yi[r])};
     }
@@ -260,34 +271,56 @@ bool is_diagonal_local(const LocalGate& lg) {
   return true;
 }
 
+template <typename R, bool DM>
+void dispatch_apply(const KronArgs& a, int k, bool diag, int64_t N, int num_cus, hipStream_t stream, void* v) {
+  using V = typename Vec<R>::V;
+  if (diag) {
+    const int64_t blocks = std::min<int64_t>((N + kBlock - 1) / kBlock, int64_t(num_cus) * 32);
+    hipLaunchKernelGGL((kron_diag_kernel<R, DM>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, a, N,
+                       static_cast<V*>(v));
+    return;
+  }
+  const int64_t blocks = (a.ncos + kBlock * kCosetsPerLane - 1) / (kBlock * kCosetsPerLane);
+  const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
+  if (k == 1)
+    hipLaunchKernelGGL((kron_apply_kernel<R, 1, DM>), grid, block, 0, stream, a, static_cast<V*>(v));
+  else if (k == 2)
+    hipLaunchKernelGGL((kron_apply_kernel<R, 2, DM>), grid, block, 0, stream, a, static_cast<V*>(v));
+  else if constexpr (!DM)
+    hipLaunchKernelGGL((kron_apply_kernel<R, 3, false>), grid, block, 0, stream, a, static_cast<V*>(v));
+}
+
+template <typename R, bool GEN, bool DM>
+void dispatch_adjoint(const KronArgs& a, int k, int64_t blocks, hipStream_t stream, void* psi, void* lam,
+                      double2* partial, int sb) {
+  using V = typename Vec<R>::V;
+  const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
+  if (k == 1)
+    hipLaunchKernelGGL((kron_adjoint_kernel<R, 1, GEN, DM>), grid, block, 0, stream, a, static_cast<V*>(psi),
+                       static_cast<V*>(lam), partial, sb);
+  else if (k == 2)
+    hipLaunchKernelGGL((kron_adjoint_kernel<R, 2, GEN, DM>), grid, block, 0, stream, a, static_cast<V*>(psi),
+                       static_cast<V*>(lam), partial, sb);
+  else if constexpr (!DM)
+    hipLaunchKernelGGL((kron_adjoint_kernel<R, 3, GEN, false>), grid, block, 0, stream, a, static_cast<V*>(psi),
+                       static_cast<V*>(lam), partial, sb);
+}
+
 }  // namespace
 
 diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
-                                void* v, bool adjoint, const DiagFactor* factors, int nf) {
-  const KronArgs a = make_args(lg, n, adjoint, factors, nf);
+                                void* v, bool adjoint, const DiagFactor* factors, int nf, const double* dmat) {
+  if (dmat && lg.k > 2) return fail(DIAQ_ERR_UNSUPPORTED, "device matrices cover at most 2 targets");
+  KronArgs a = make_args(lg, n, adjoint, factors, nf);
+  a.dmat = dmat;
   const int64_t N = int64_t(1) << n;
-  if (is_diagonal_local(lg)) {
-    const int64_t blocks = std::min<int64_t>((N + kBlock - 1) / kBlock, int64_t(ctx->num_cus) * 32);
-    if (dt == DIAQ_C128)
-      hipLaunchKernelGGL(kron_diag_kernel<double>, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, a, N,
-                         static_cast<double2*>(v));
-    else
-      hipLaunchKernelGGL(kron_diag_kernel<float>, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, a, N,
-                         static_cast<float2*>(v));
+  const bool diag = is_diagonal_local(lg);
+  if (dt == DIAQ_C128) {
+    if (dmat) dispatch_apply<double, true>(a, lg.k, diag, N, ctx->num_cus, stream, v);
+    else dispatch_apply<double, false>(a, lg.k, diag, N, ctx->num_cus, stream, v);
   } else {
-    const int64_t blocks = (a.ncos + kBlock * kCosetsPerLane - 1) / (kBlock * kCosetsPerLane);
-    const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
-#define DIAQ_KRON(R, K, PTR) hipLaunchKernelGGL((kron_apply_kernel<R, K>), grid, block, 0, stream, a, static_cast<PTR*>(v))
-    if (dt == DIAQ_C128) {
-      if (lg.k == 1) DIAQ_KRON(double, 1, double2);
-      else if (lg.k == 2) DIAQ_KRON(double, 2, double2);
-      else DIAQ_KRON(double, 3, double2);
-    } else {
-      if (lg.k == 1) DIAQ_KRON(float, 1, float2);
-      else if (lg.k == 2) DIAQ_KRON(float, 2, float2);
-      else DIAQ_KRON(float, 3, float2);
-    }
-#undef DIAQ_KRON
+    if (dmat) dispatch_apply<float, true>(a, lg.k, diag, N, ctx->num_cus, stream, v);
+    else dispatch_apply<float, false>(a, lg.k, diag, N, ctx->num_cus, stream, v);
   }
   DIAQ_HIP(hipGetLastError());
   return DIAQ_OK;
@@ -299,38 +332,32 @@ int64_t kron_adjoint_blocks(const LocalGate& lg, int n) {
 }
 
 diaq_status_t launch_kron_adjoint(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, const LocalGate* gen, int n,
-                                  diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back) {
+                                  diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back,
+                                  const double* dmat) {
   (void)ctx;
+  if (dmat && lg.k > 2) return fail(DIAQ_ERR_UNSUPPORTED, "device matrices cover at most 2 targets");
   KronArgs a = make_args(lg, n, true, nullptr, 0);
+  a.dmat = dmat;
   if (gen) std::memcpy(a.g, gen->m, sizeof(a.g));
   const int64_t blocks = kron_adjoint_blocks(lg, n);
-  const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
   const int sb = step_back ? 1 : 0;
-#define DIAQ_KADJ(R, K, G, PTR)                                                                           \
-  hipLaunchKernelGGL((kron_adjoint_kernel<R, K, G>), grid, block, 0, stream, a, static_cast<PTR*>(psi), \
-                     static_cast<PTR*>(lam), partial, sb)
   if (dt == DIAQ_C128) {
     if (gen) {
-      if (lg.k == 1) DIAQ_KADJ(double, 1, true, double2);
-      else if (lg.k == 2) DIAQ_KADJ(double, 2, true, double2);
-      else DIAQ_KADJ(double, 3, true, double2);
+      if (dmat) dispatch_adjoint<double, true, true>(a, lg.k, blocks, stream, psi, lam, partial, sb);
+      else dispatch_adjoint<double, true, false>(a, lg.k, blocks, stream, psi, lam, partial, sb);
     } else {
-      if (lg.k == 1) DIAQ_KADJ(double, 1, false, double2);
-      else if (lg.k == 2) DIAQ_KADJ(double, 2, false, double2);
-      else DIAQ_KADJ(double, 3, false, double2);
+      if (dmat) dispatch_adjoint<double, false, true>(a, lg.k, blocks, stream, psi, lam, partial, sb);
+      else dispatch_adjoint<double, false, false>(a, lg.k, blocks, stream, psi, lam, partial, sb);
     }
   } else {
     if (gen) {
-      if (lg.k == 1) DIAQ_KADJ(float, 1, true, float2);
-      else if (lg.k == 2) DIAQ_KADJ(float, 2, true, float2);
-      else DIAQ_KADJ(float, 3, true, float2);
+      if (dmat) dispatch_adjoint<float, true, true>(a, lg.k, blocks, stream, psi, lam, partial, sb);
+      else dispatch_adjoint<float, true, false>(a, lg.k, blocks, stream, psi, lam, partial, sb);
     } else {
-      if (lg.k == 1) DIAQ_KADJ(float, 1, false, float2);
-      else if (lg.k == 2) DIAQ_KADJ(float, 2, false, float2);
-      else DIAQ_KADJ(float, 3, false, float2);
+      if (dmat) dispatch_adjoint<float, false, true>(a, lg.k, blocks, stream, psi, lam, partial, sb);
+      else dispatch_adjoint<float, false, false>(a, lg.k, blocks, stream, psi, lam, partial, sb);
     }
   }
-#undef DIAQ_KADJ
   DIAQ_HIP(hipGetLastError());
   return DIAQ_OK;
 }

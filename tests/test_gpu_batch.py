@@ -116,6 +116,29 @@ def test_batch_general_gates():
             assert np.max(np.abs(grads[i] - ps)) <= 1e-10 * max(1.0, np.max(np.abs(ps)))
 
 
+def test_batch_wide_circuits_on_side_streams():
+    """Circuits of 15+ qubits run gate by gate with the grid-wide Alg. 3
+    kernels on side streams, next to the persistent kernel."""
+    insts, circs, theta = _qaoa_circuits(10, 77, widths=(8, 12, 16, 18), pmax=2)
+    rng = np.random.default_rng(78)
+    for graph in (False, True):
+        b = D.Batch(circs, graph=graph)
+        for rep in range(2):
+            th = theta if rep == 0 else rng.uniform(0, math.pi, theta.size)
+            ev, grads = b.run(th)
+            k = 0
+            for i, inst in enumerate(insts):
+                t = th[k:k + 2 * inst.p]
+                k += 2 * inst.p
+                gates = W.qaoa_gates(inst.n, inst.edges, t[0::2], t[1::2])
+                psi0 = W.zero_state(inst.n)
+                e = orc.energy(psi0, inst.n, gates, inst.terms)
+                assert abs(ev[i] - e) <= 1e-11 * max(1.0, abs(e)), (graph, rep, inst.n)
+                if inst.n == 16 and rep == 0:
+                    ps = orc.param_shift_grad(psi0, inst.n, gates, inst.terms, 2 * inst.p)
+                    assert np.max(np.abs(grads[i] - ps)) <= 1e-10 * max(1.0, np.max(np.abs(ps))), (graph, inst.n)
+
+
 def test_batch_rejects_wide_gates():
     with pytest.raises(D.DiaqError):
         D.Batch([(6, [W.Gate("MATRIX", (0, 1, 2), matrix=np.eye(8))], [(0, 1, 1.0)], 0)])
