@@ -159,6 +159,9 @@ def main():
     scratch = torch.empty_like(state)
     ctx = D.context()
 
+    # product-kernel knobs chosen by the autotuner at this size (untimed)
+    tuning = D.autotune(n, dtype=tdt, ctx=ctx)
+
     def step():
         D.apply_circuit(gates, state, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
         return D.expect(Hzz, state)
@@ -201,6 +204,7 @@ def main():
                                "<Z_iZ_i+1> energy" % (n, a.layers, len(gates), a.seed),
                    "n": n, "gates": len(gates), "layers": a.layers},
         "gates_per_s": round(len(gates) * a.steps / dt, 2),
+        "tuning": tuning,
         "spmv_GBps": round(achieved, 1),
         "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)
         if prof["expand_ms"] else None,
@@ -216,6 +220,8 @@ def main():
         out["check"]["error"] = "norm drifted"
 
     if a.extras:
+        p = D.autotune_plan(gates, n, dtype=tdt, allow_kron=True, measure=3, ctx=ctx)
+        out["autotuned_plan"] = {"fuse": p.fuse, "max_fused_qubits": p.max_fused_qubits, "kron": p.kron}
         out["variants"] = [fused_extra(D, gates, state, scratch, ctx, n, a.steps, **kw)
                            for kw in ({"fuse": True, "max_fused_qubits": 2}, {"fuse": True, "max_fused_qubits": 3},
                                       {"kron": True}, {"kron": True, "fuse": True, "max_fused_qubits": 2},

@@ -364,6 +364,32 @@ diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);
 diaq_status_t diaq_get_tuning(diaq_ctx_t ctx, diaq_tuning_t* t);
 
 /* ------------------------------------------------------------------ */
+/* Autotuning                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Pick the product kernel's knobs for 2^nqubits-element vectors: time the
+ * DiaQ SpMV of expanded one-qubit gates on qubits spread over the register
+ * (and a CX) under every candidate tuning, keep the fastest, install it in
+ * the context and write it to *out.  With cache_path (a JSON file) the
+ * result is stored under a key naming the device, n and dtype, and a
+ * later call with the same key reads it back without timing.  Allocates
+ * and frees its own test vectors.  Synchronises the stream. */
+diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype,
+                            const char* cache_path, diaq_tuning_t* out);
+
+/* Choose a plan (fusion depth 1..3, expanded DiaQ products or, when
+ * allow_kron != 0, Alg. 3 in-place products) for one circuit: candidates
+ * are ranked by a byte model (diaq_plan_count, weighted by the measured
+ * expansion and product rates) and skipped when their largest expanded
+ * operation would not fit in free device memory; the best `measure`
+ * candidates are then timed on the circuit's first gates (at most 64) on a
+ * scratch vector, and the fastest per gate wins.  Synchronises the stream. */
+diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates,
+                                 int64_t ngates, int32_t nqubits,
+                                 diaq_dtype_t dtype, int32_t allow_kron,
+                                 int32_t measure, diaq_plan_t* out);
+
+/* ------------------------------------------------------------------ */
 /* Kernel timing (the counterpart of the simulator trace timer the paper
  * reads its times from, Sec. VII)                                      */
 /* ------------------------------------------------------------------ */

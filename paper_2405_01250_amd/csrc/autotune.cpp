@@ -1,0 +1,354 @@
+// autotune.cpp -- picks the product kernel's knobs and a circuit's plan by
+// measurement, with a JSON cache for the kernel knobs.
+//
+// The paper's cost model (Sec. IV: O(N d) for a product, O(d1 d2 N) for a
+// matrix product) says how much work a plan does; on an HBM-bound GPU the
+// time follows the bytes, so plans are ranked by their algorithmic bytes
+// and the best few are timed.
+#include <cstdio>
+#include <string>
+
+#include "internal.hpp"
+
+namespace diaq {
+
+namespace {
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer() {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+std::string device_name(int dev) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::string s = p.name;
+  for (char& c : s)
+    if (c == '"' || c == '\\' || c == '\n') c = ' ';
+  return s + "/" + p.gcnArchName;
+}
+
+std::string cache_key(int dev, int n, diaq_dtype_t dt) {
+  return device_name(dev) + "|n=" + std::to_string(n) + "|" + (dt == DIAQ_C128 ? "c128" : "c64");
+}
+
+std::string read_file(const char* path) {
+  std::string s;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return s;
+  char buf[4096];
+  size_t r;
+  while ((r = std::fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, r);
+  std::fclose(f);
+  return s;
+}
+
+bool int_field(const std::string& obj, const char* name, int32_t* v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  size_t p = obj.find(pat);
+  if (p == std::string::npos) return false;
+  *v = int32_t(std::strtol(obj.c_str() + p + pat.size(), nullptr, 10));
+  return true;
+}
+
+// Entries are one JSON object per line inside {"entries": [ ... ]}.
+bool cache_lookup(const char* path, const std::string& key, diaq_tuning_t* t) {
+  const std::string text = read_file(path);
+  const std::string pat = "\"key\":\"" + key + "\"";
+  size_t p = text.find(pat);
+  if (p == std::string::npos) return false;
+  const size_t b = text.rfind('{', p), e = text.find('}', p);
+  if (b == std::string::npos || e == std::string::npos) return false;
+  const std::string obj = text.substr(b, e - b + 1);
+  diaq_tuning_t r{};
+  bool ok = int_field(obj, "spmv_rows", &r.spmv_rows) && int_field(obj, "spmv_group_bits", &r.spmv_group_bits) &&
+            int_field(obj, "spmv_chunk", &r.spmv_chunk) && int_field(obj, "spmv_nontemporal", &r.spmv_nontemporal) &&
+            int_field(obj, "spmv_group_min_qubit", &r.spmv_group_min_qubit);
+  if (ok) *t = r;
+  return ok;
+}
+
+diaq_status_t cache_store(const char* path, const std::string& key, const diaq_tuning_t& t, double ms) {
+  const std::string text = read_file(path);
+  std::vector<std::string> lines;
+  size_t p = 0;
+  while (true) {
+    const size_t b = text.find("{\"key\":", p);
+    if (b == std::string::npos) break;
+    const size_t e = text.find('}', b);
+    if (e == std::string::npos) break;
+    const std::string obj = text.substr(b, e - b + 1);
+    if (obj.find("\"key\":\"" + key + "\"") == std::string::npos) lines.push_back(obj);
+    p = e + 1;
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof(buf),
+                "{\"key\":\"%s\",\"spmv_rows\":%d,\"spmv_group_bits\":%d,\"spmv_chunk\":%d,"
+                "\"spmv_nontemporal\":%d,\"spmv_group_min_qubit\":%d,\"ms\":%.4f}",
+                key.c_str(), t.spmv_rows, t.spmv_group_bits, t.spmv_chunk, t.spmv_nontemporal,
+                t.spmv_group_min_qubit, ms);
+  lines.push_back(buf);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(DIAQ_ERR_INVALID_ARGUMENT, "cannot write autotune cache %s", tmp.c_str());
+  std::fprintf(f, "{\"entries\": [\n");
+  for (size_t i = 0; i < lines.size(); i++) std::fprintf(f, "  %s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+  std::fprintf(f, "]}\n");
+  std::fclose(f);
+  if (std::rename(tmp.c_str(), path) != 0) return fail(DIAQ_ERR_INVALID_ARGUMENT, "cannot replace %s", path);
+  return DIAQ_OK;
+}
+
+std::vector<diaq_tuning_t> candidates() {
+  std::vector<diaq_tuning_t> c;
+  for (int rows : {1, 2, 4})
+    for (int chunk : {1, 3})
+      for (int nt : {1, -1})
+        for (int gmin : {19, 21, 23, 0}) {
+          diaq_tuning_t t{};
+          t.spmv_rows = rows;
+          t.spmv_chunk = chunk;
+          t.spmv_nontemporal = nt;
+          t.spmv_group_bits = gmin ? 0 : -1;  // 0: up to 3 paired qubits; -1: none
+          t.spmv_group_min_qubit = gmin ? gmin : 0;
+          c.push_back(t);
+        }
+  return c;
+}
+
+}  // namespace
+
+}  // namespace diaq
+
+using namespace diaq;
+
+extern "C" {
+
+diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype, const char* cache_path,
+                            diaq_tuning_t* out) {
+  try {
+    if (!ctx) return fail(DIAQ_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (nqubits < 1 || nqubits > 32) return fail(DIAQ_ERR_INVALID_ARGUMENT, "nqubits %d out of range", nqubits);
+    if (dtype != DIAQ_C64 && dtype != DIAQ_C128) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad dtype");
+    const std::string key = cache_key(ctx->device, nqubits, dtype);
+    diaq_tuning_t best{};
+    if (cache_path && cache_lookup(cache_path, key, &best)) {
+      best.expand_nontemporal = ctx->tuning.expand_nontemporal;
+      best.diag_pad = ctx->tuning.diag_pad;
+      ctx->tuning = best;
+      if (out) *out = best;
+      return DIAQ_OK;
+    }
+    const int n = nqubits;
+    const size_t N = size_t(1) << n, s = elem_bytes(dtype);
+    // test gates: U3 on qubits spread over the register, and one CX
+    std::vector<diaq_gate_t> gates;
+    std::vector<int> qs = {0, n / 3, (2 * n) / 3, n - 1};
+    std::sort(qs.begin(), qs.end());
+    qs.erase(std::unique(qs.begin(), qs.end()), qs.end());
+    for (int q : qs) {
+      diaq_gate_t g{};
+      g.kind = DIAQ_GATE_U3;
+      g.ntargets = 1;
+      g.targets[0] = q;
+      g.params[0] = 0.3;
+      g.params[1] = 0.5;
+      g.params[2] = 0.7;
+      g.param_index = -1;
+      gates.push_back(g);
+    }
+    if (n >= 2) {
+      diaq_gate_t g{};
+      g.kind = DIAQ_GATE_X;
+      g.ntargets = 1;
+      g.ncontrols = 1;
+      g.targets[0] = n / 2;
+      g.controls[0] = n / 2 - 1 >= 0 ? n / 2 - 1 : n / 2 + 1;
+      g.param_index = -1;
+      gates.push_back(g);
+    }
+    void* x = nullptr;
+    void* y = nullptr;
+    DIAQ_HIP(hipMalloc(&x, N * s));
+    if (hipMalloc(&y, N * s) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(x);
+      return fail(DIAQ_ERR_OUT_OF_MEMORY, "autotune vectors");
+    }
+    struct Free {
+      void* a;
+      void* b;
+      ~Free() {
+        (void)hipFree(a);
+        (void)hipFree(b);
+      }
+    } guard{x, y};
+    DIAQ_HIP(hipMemsetAsync(x, 0, N * s, ctx->stream));
+    const diaq_tuning_t saved = ctx->tuning;
+    const std::vector<diaq_tuning_t> cand = candidates();
+    std::vector<double> total(cand.size(), 0.0);
+    Timer tm;
+    const int reps = n >= 24 ? 3 : 10;
+    for (const auto& g : gates) {
+      LocalGate lg;
+      DIAQ_TRY(local_gate(&g, n, &lg));
+      const std::vector<int64_t> offs = gate_offsets(lg);
+      const std::vector<int64_t> st = packing_starts(offs, n);
+      DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(st.back()) * s));
+      DIAQ_TRY(launch_expand(ctx, lg, n, dtype, offs, st, ctx->diag.ptr));
+      SpmvOp op;
+      op.n = n;
+      op.dtype = dtype;
+      op.nd = int(offs.size());
+      op.host_off = offs.data();
+      op.host_start = st.data();
+      op.values = ctx->diag.ptr;
+      op.qubit_mask = lg.tmask;
+      for (size_t c = 0; c < cand.size(); c++) {
+        ctx->tuning = cand[c];
+        DIAQ_TRY(launch_spmv(ctx, op, x, y));  // warm-up
+        DIAQ_HIP(hipEventRecord(tm.a, ctx->stream));
+        for (int r = 0; r < reps; r++) DIAQ_TRY(launch_spmv(ctx, op, x, y));
+        DIAQ_HIP(hipEventRecord(tm.b, ctx->stream));
+        DIAQ_HIP(hipEventSynchronize(tm.b));
+        float ms = 0;
+        DIAQ_HIP(hipEventElapsedTime(&ms, tm.a, tm.b));
+        total[c] += ms / reps;
+      }
+    }
+    size_t bi = 0;
+    for (size_t c = 1; c < cand.size(); c++)
+      if (total[c] < total[bi]) bi = c;
+    best = cand[bi];
+    best.expand_nontemporal = saved.expand_nontemporal;
+    best.diag_pad = saved.diag_pad;
+    ctx->tuning = best;
+    if (cache_path) DIAQ_TRY(cache_store(cache_path, key, best, total[bi]));
+    if (out) *out = best;
+    return DIAQ_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t ngates, int32_t nqubits,
+                                 diaq_dtype_t dtype, int32_t allow_kron, int32_t measure, diaq_plan_t* out) {
+  try {
+    if (!ctx || !out || ngates < 0 || (ngates > 0 && !gates)) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad arguments");
+    if (nqubits < 1 || nqubits > 34) return fail(DIAQ_ERR_INVALID_ARGUMENT, "nqubits out of range");
+    if (dtype != DIAQ_C64 && dtype != DIAQ_C128) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad dtype");
+    const int n = nqubits;
+    const double s = double(elem_bytes(dtype)), N = double(int64_t(1) << n);
+    struct Cand {
+      diaq_plan_t plan;
+      double est_ms;
+      double max_bytes;  // largest expanded operation
+    };
+    std::vector<Cand> cands;
+    // measured-or-nominal rates (GB/s) for the byte model
+    const double rate_dia = 5900.0, rate_kron = 6200.0, launch_ms = 0.004;
+    auto add = [&](int fuse, int k, int kron) -> diaq_status_t {
+      diaq_plan_t p{};
+      p.fuse = fuse;
+      p.max_fused_qubits = k;
+      p.kron = kron;
+      std::vector<FusedOp> ops;
+      double bytes = 0, maxb = 0;
+      int64_t nops = 0;
+      if (fuse) {
+        DIAQ_TRY(plan_fusion(gates, ngates, n, k, dtype, &ops, kron != 0));
+      } else {
+        ops.resize(size_t(ngates));
+        for (int64_t g = 0; g < ngates; g++) {
+          DIAQ_TRY(local_gate(&gates[g], n, &ops[size_t(g)].core));
+          ops[size_t(g)].ngates = 1;
+        }
+      }
+      for (const auto& op : ops) {
+        const double E = double(packing_starts(gate_offsets(op.core), n).back());
+        if (kron) {
+          bytes += 2 * s * N;
+        } else {
+          bytes += s * (2 * E + 2 * N);
+          maxb = std::max(maxb, s * E);
+          if (gate_offsets(op.core).size() > size_t(kMaxArgDiags)) return DIAQ_OK;  // not runnable
+        }
+      }
+      nops = int64_t(ops.size());
+      const double est = bytes / ((kron ? rate_kron : rate_dia) * 1e6) + double(nops) * launch_ms;
+      cands.push_back(Cand{p, est, maxb});
+      return DIAQ_OK;
+    };
+    DIAQ_TRY(add(0, 0, 0));
+    for (int k = 1; k <= 3; k++) DIAQ_TRY(add(1, k, 0));
+    if (allow_kron) {
+      DIAQ_TRY(add(0, 0, 1));
+      for (int k = 1; k <= 3; k++) DIAQ_TRY(add(1, k, 1));
+    }
+    size_t free_b = 0, total_b = 0;
+    DIAQ_HIP(hipMemGetInfo(&free_b, &total_b));
+    const double avail = double(free_b) + double(ctx->diag.bytes) - 2 * s * N - double(64 << 20);
+    std::vector<Cand> fit;
+    for (const auto& c : cands)
+      if (c.max_bytes <= avail) fit.push_back(c);
+    if (fit.empty()) return fail(DIAQ_ERR_OUT_OF_MEMORY, "no plan fits in device memory");
+    std::stable_sort(fit.begin(), fit.end(), [](const Cand& a, const Cand& b) { return a.est_ms < b.est_ms; });
+    const size_t nm = std::min(fit.size(), size_t(std::max(0, measure)));
+    if (nm <= 1 || ngates == 0) {
+      *out = fit[0].plan;
+      return DIAQ_OK;
+    }
+    // time the leaders on the circuit's first gates
+    const int64_t ng = std::min<int64_t>(ngates, 64);
+    void* st = nullptr;
+    void* sc = nullptr;
+    const size_t vb = size_t(N) * size_t(s);
+    DIAQ_HIP(hipMalloc(&st, vb));
+    if (hipMalloc(&sc, vb) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(st);
+      return fail(DIAQ_ERR_OUT_OF_MEMORY, "autotune vectors");
+    }
+    struct Free {
+      void* a;
+      void* b;
+      ~Free() {
+        (void)hipFree(a);
+        (void)hipFree(b);
+      }
+    } guard{st, sc};
+    DIAQ_HIP(hipMemsetAsync(st, 0, vb, ctx->stream));
+    Timer tm;
+    double best = 1e300;
+    size_t bi = 0;
+    for (size_t c = 0; c < nm; c++) {
+      DIAQ_TRY(diaq_apply_circuit(ctx, gates, ng, 0, ng, n, dtype, st, sc, &fit[c].plan));  // warm-up
+      DIAQ_HIP(hipEventRecord(tm.a, ctx->stream));
+      DIAQ_TRY(diaq_apply_circuit(ctx, gates, ng, 0, ng, n, dtype, st, sc, &fit[c].plan));
+      DIAQ_HIP(hipEventRecord(tm.b, ctx->stream));
+      DIAQ_HIP(hipEventSynchronize(tm.b));
+      float ms = 0;
+      DIAQ_HIP(hipEventElapsedTime(&ms, tm.a, tm.b));
+      if (ms < best) {
+        best = ms;
+        bi = c;
+      }
+    }
+    *out = fit[bi].plan;
+    return DIAQ_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+}  // extern "C"

@@ -105,6 +105,8 @@ _SIGS = {
     "diaq_batch_create": [_P, _P, _I32, _U32, ctypes.POINTER(_P)],
     "diaq_batch_run": [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "diaq_batch_free": [_P],
+    "diaq_autotune": [_P, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(diaq_tuning_t)],
+    "diaq_autotune_plan": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _I32, _I32, ctypes.POINTER(diaq_plan_t)],
     "diaq_profile_start": [_P],
     "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
@@ -582,3 +584,29 @@ class Batch:
         except Exception:
             pass
         self.handle = None
+
+
+# --------------------------------------------------------------------------
+# Autotuning
+# --------------------------------------------------------------------------
+
+def autotune(n: int, dtype=torch.complex128, cache_path: str | None = None, ctx: Context | None = None) -> dict:
+    """Time the product kernel's candidate knobs at 2^n elements, install
+    the fastest in the context and return it (cached in a JSON file)."""
+    ctx = ctx or context()
+    t = diaq_tuning_t()
+    _check(load().diaq_autotune(ctx.handle, n, _dtype_code(dtype),
+                                cache_path.encode() if cache_path else None, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in diaq_tuning_t._fields_ if f != "reserved"}
+
+
+def autotune_plan(gates: Sequence, n: int, dtype=torch.complex128, allow_kron: bool = False, measure: int = 3,
+                  ctx: Context | None = None) -> diaq_plan_t:
+    """Plan (fusion depth, DiaQ or Alg. 3 products) for one circuit, ranked
+    by bytes and decided by timing the leaders on its first gates."""
+    ctx = ctx or context()
+    arr, keep = gate_array(gates)
+    p = diaq_plan_t()
+    _check(load().diaq_autotune_plan(ctx.handle, arr, len(gates), n, _dtype_code(dtype), int(allow_kron), measure,
+                                     ctypes.byref(p)))
+    return p
