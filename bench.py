@@ -43,6 +43,8 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="time budget of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--extras", type=int, default=1, help="also time adjoint vs parameter shift (HEA n=20)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of autotuned product-kernel knobs (read if it holds this size, else written)")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
                     help="copy: run a plain device copy of 2^n complex elements (counter calibration)")
     return ap.parse_args()
@@ -160,7 +162,7 @@ def main():
     ctx = D.context()
 
     # product-kernel knobs chosen by the autotuner at this size (untimed)
-    tuning = D.autotune(n, dtype=tdt, ctx=ctx)
+    tuning = D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
 
     def step():
         D.apply_circuit(gates, state, n=n, scratch=scratch, marshalled=arr, ctx=ctx)

@@ -26,16 +26,18 @@ struct Timer {
   }
 };
 
+// The key names the architecture and compute-unit count; the marketing
+// name is left out because some tool environments report it empty.
 std::string device_name(int dev) {
   hipDeviceProp_t p;
   if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
     (void)hipGetLastError();
     return "unknown";
   }
-  std::string s = p.name;
+  std::string s = p.gcnArchName;
   for (char& c : s)
     if (c == '"' || c == '\\' || c == '\n') c = ' ';
-  return s + "/" + p.gcnArchName;
+  return s + "/cu" + std::to_string(p.multiProcessorCount);
 }
 
 std::string cache_key(int dev, int n, diaq_dtype_t dt) {
