@@ -157,14 +157,27 @@ void orc_pauli_sum_apply(int n, int nterms, const uint64_t *xmask,
     }
 }
 
-/* <a|b> = sum_i conj(a_i) b_i, summed sequentially in index order. */
+/* One step of Neumaier's compensated summation: s + c carries the running
+ * sum with its rounding error, so a 2^28-term sum stays within a few ulps
+ * instead of drifting by up to N ulps. */
+static void neumaier_add(double *s, double *c, double v)
+{
+    double t = *s + v;
+    if (fabs(*s) >= fabs(v))
+        *c += (*s - t) + v;
+    else
+        *c += (v - t) + *s;
+    *s = t;
+}
+
+/* <a|b> = sum_i conj(a_i) b_i, summed in index order with compensation. */
 void orc_inner(int64_t N, const double *a, const double *b, double *out)
 {
-    double sr = 0.0, si = 0.0;
+    double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
     for (int64_t i = 0; i < N; i++) {
-        sr += a[2 * i] * b[2 * i] + a[2 * i + 1] * b[2 * i + 1];
-        si += a[2 * i] * b[2 * i + 1] - a[2 * i + 1] * b[2 * i];
+        neumaier_add(&sr, &cr, a[2 * i] * b[2 * i] + a[2 * i + 1] * b[2 * i + 1]);
+        neumaier_add(&si, &ci, a[2 * i] * b[2 * i + 1] - a[2 * i + 1] * b[2 * i]);
     }
-    out[0] = sr;
-    out[1] = si;
+    out[0] = sr + cr;
+    out[1] = si + ci;
 }

@@ -333,6 +333,24 @@ def test_hh_is_identity(orc):
 # Observables
 # --------------------------------------------------------------------------
 
+def test_inner_product_is_compensated(orc):
+    """<a|a> for a = (1, 2^-30, ..., 2^-30) with 2^20 small entries is
+    1 + 2^-40 exactly; every small square is below half an ulp of 1, so a
+    plain running sum would return 1.  Random vectors agree with an exactly
+    rounded sum (math.fsum) of the same products to a few ulps."""
+    a = np.full(1 + (1 << 20), 2.0 ** -30, dtype=np.complex128)
+    a[0] = 1.0
+    assert orc.inner(a, a) == complex(1 + 2.0 ** -40, 0.0)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(1 << 18) + 1j * rng.standard_normal(1 << 18)
+    y = rng.standard_normal(1 << 18) + 1j * rng.standard_normal(1 << 18)
+    re = math.fsum(x.real * y.real + x.imag * y.imag)
+    im = math.fsum(x.real * y.imag - x.imag * y.real)
+    got = orc.inner(x, y)
+    eps = np.finfo(float).eps
+    assert abs(got.real - re) <= 4 * eps * abs(re) and abs(got.imag - im) <= 4 * eps * abs(im)
+
+
 def test_pauli_apply_matches_dense(orc):
     rng = np.random.default_rng(21)
     n = 6
@@ -425,3 +443,49 @@ def test_qaoa_p1_closed_form(orc):
             e = orc.energy(W.zero_state(n), n, gates, W.maxcut_terms(edges))
             assert abs(e - _qaoa_p1_closed_form(n, edges, gamma, beta)) < 1e-11
             assert -1e-12 <= e <= len(edges) + 1e-12
+
+
+# --------------------------------------------------------------------------
+# TFIM Trotter workload (Hamiltonian simulation, 1D transverse-field Ising)
+# --------------------------------------------------------------------------
+
+def test_tfim_trotter_converges_to_exact_evolution(orc):
+    """First-order Trotter product against exp(-i t H) from a dense
+    matrix exponential: the error stays below t^2/(2s) ||[A, B]|| (A the
+    ZZ part, B the field part) and halves when the step count doubles.  A
+    sign slip in either angle makes the error O(1)."""
+    n, t, J, hx = 6, 0.8, 1.0, 0.7
+    terms = W.tfim_terms(n, J, hx)
+    A = pins.hamiltonian_dense(n, [tm for tm in terms if tm[0] == 0])
+    B = pins.hamiltonian_dense(n, [tm for tm in terms if tm[0] != 0])
+    comm = np.linalg.norm(A @ B - B @ A, 2)
+    x = W.random_state(n, 6)
+    exact = scipy.linalg.expm(-1j * t * (A + B)) @ x
+    errs = []
+    for s in (8, 16, 32):
+        got = orc.apply_circuit(x, n, W.tfim(n, s, t / s, J, hx))
+        e = np.linalg.norm(got - exact)
+        assert e <= t * t / (2 * s) * comm, (s, e)
+        errs.append(e)
+    assert 0.4 < errs[1] / errs[0] < 0.6 and 0.4 < errs[2] / errs[1] < 0.6, errs
+
+
+def test_tfim_without_coupling_closed_form(orc):
+    """J = 0: independent spins precessing about x, so from |0..0> each
+    <Z_i> = cos(2 hx t)."""
+    n, s, dt, hx = 7, 9, 0.07, 1.3
+    psi = orc.apply_circuit(W.zero_state(n), n, W.tfim(n, s, dt, J=0.0, hx=hx))
+    m = orc.expect(n, W.magnetization_terms(n), psi).real
+    assert abs(m - math.cos(2 * hx * s * dt)) < 1e-13
+
+
+def test_tfim_without_field_is_a_phase(orc):
+    """hx = 0: the evolution is diagonal, amplitude j picks up
+    exp(i J t sum_i z_i z_{i+1}) with z = 1 - 2 bit."""
+    n, s, dt, J = 8, 5, 0.11, 0.9
+    x = W.random_state(n, 8)
+    got = orc.apply_circuit(x, n, W.tfim(n, s, dt, J=J, hx=0.0))
+    j = np.arange(1 << n)
+    z = 1 - 2 * ((j[:, None] >> np.arange(n)) & 1)
+    want = x * np.exp(1j * J * s * dt * np.sum(z[:, :-1] * z[:, 1:], axis=1))
+    assert np.max(np.abs(got - want)) < 1e-14
