@@ -228,6 +228,7 @@ def main():
                            for kw in ({"fuse": True, "max_fused_qubits": 2}, {"fuse": True, "max_fused_qubits": 3},
                                       {"kron": True}, {"kron": True, "fuse": True, "max_fused_qubits": 2},
                                       {"kron": True, "fuse": True, "max_fused_qubits": 3})]
+        out["tfim"] = tfim_extra(D, W, torch, ctx, state, scratch, tdt)
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
         out["batch"] = batch_extra(D, W, torch, dev)
     if a.cpu_seconds > 0:
@@ -262,6 +263,40 @@ def fused_extra(D, gates, state, scratch, ctx, n, steps, **kw):
             "product_GBps": round(prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9, 1) if prof["spmv_ms"] else None,
             "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)
             if prof["expand_ms"] else None}
+
+
+def tfim_extra(D, W, torch, ctx, state, scratch, tdt):
+    """Hamiltonian-simulation workload: Trotterised 1D TFIM (28 spins,
+    J = hx = 1, 20 steps of dt = 0.05, 1100 gates) from |0..0>, run under
+    each plan; the average magnetization must agree across plans."""
+    n, steps, dt_ = W.TFIM_N, W.TFIM_STEPS, W.TFIM_DT
+    gates = W.tfim(n, steps, dt_)
+    M = D.from_pauli_sum(n, W.magnetization_terms(n), dtype=tdt)
+    arr = D.gate_array(gates)
+    out = {"workload": "1D TFIM Trotter circuit, n=%d, %d steps of dt=%g, J=hx=1, |0..0>, %d gates "
+                       "(RZZ chain + RX layer per step); observable: average magnetization" % (n, steps, dt_, len(gates)),
+           "gates": len(gates), "plans": []}
+    mags = []
+    for kw in ({}, {"fuse": True, "max_fused_qubits": 3}, {"kron": True},
+               {"kron": True, "fuse": True, "max_fused_qubits": 3}):
+        plan = D.make_plan(**kw) if kw else None
+        nops, nbytes = D.plan_count(gates, n, plan, dtype=tdt)
+        for _ in range(2):  # the first run sizes the workspaces; the second is timed
+            state.zero_()
+            state[0] = 1
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            D.apply_circuit(gates, state, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        mags.append(D.expect(M, state).real)
+        out["plans"].append({"plan": ("kron" if kw.get("kron") else "dia")
+                             + ("+fuse%d" % kw["max_fused_qubits"] if kw.get("fuse") else ""),
+                             "ops": nops, "ms": round(dt * 1e3, 2), "gates_per_s": round(len(gates) / dt, 1),
+                             "GBps": round(nbytes / dt / 1e9, 1)})
+    out["magnetization"] = mags[0]
+    out["max_magnetization_diff"] = max(abs(m - mags[0]) for m in mags)
+    return out
 
 
 def batch_extra(D, W, torch, dev, reps=3):

@@ -242,8 +242,10 @@ def qaoa_batch(count: int = 512, seed: int = 512, widths=(10, 12, 14, 16, 18, 20
 
 
 def tfim(n: int, steps: int, dt: float = 0.1, J: float = 1.0, hx: float = 1.0):
-    """First-order Trotter steps of H = -J sum Z_i Z_{i+1} - hx sum X_i:
-    each step RZZ(-2 J dt) on (i, i+1), then RX(-2 hx dt) on every qubit."""
+    """First-order Trotter steps of the open-chain transverse-field Ising
+    model H = -J sum Z_i Z_{i+1} - hx sum X_i: each step RZZ(-2 J dt) on
+    (i, i+1), then RX(-2 hx dt) on every qubit, so that one step is
+    exp(i J dt sum ZZ) followed by exp(i hx dt sum X)."""
     gates = []
     for _ in range(steps):
         for i in range(n - 1):
@@ -251,3 +253,20 @@ def tfim(n: int, steps: int, dt: float = 0.1, J: float = 1.0, hx: float = 1.0):
         for q in range(n):
             gates.append(Gate("RX", (q,), (), (-2.0 * hx * dt,)))
     return gates
+
+
+def tfim_terms(n: int, J: float = 1.0, hx: float = 1.0):
+    """The same Hamiltonian as Pauli terms [(xmask, zmask, coef)]."""
+    return ([(0, (1 << i) | (1 << (i + 1)), -J) for i in range(n - 1)]
+            + [(1 << q, 0, -hx) for q in range(n)])
+
+
+def magnetization_terms(n: int):
+    """Average magnetization (1/n) sum Z_i, the observable of the
+    Hamiltonian-simulation benchmark."""
+    return [(0, 1 << q, 1.0 / n) for q in range(n)]
+
+
+# The TFIM workload the benchmark times: 28 spins at the critical field
+# (J = hx = 1), 20 Trotter steps of dt = 0.05 from |0..0> (1100 gates).
+TFIM_N, TFIM_STEPS, TFIM_DT = 28, 20, 0.05
