@@ -21,6 +21,11 @@ What each function follows
 * ``pauli_apply`` / ``expect`` / ``energy`` -- <psi|H|phi> for a Pauli sum.
 * ``param_shift_grad`` / ``fd_grad`` -- gradients of <H> by the two-term
   parameter-shift rule and by central differences.
+* ``unitary_chain`` / ``density_chain`` / ``count_diagonals`` /
+  ``count_nonzeros`` / ``trace_product`` -- matrix-level simulation
+  (Sec. II-B): the circuit unitary as the running dense product of the
+  time-step matrices, rho <- G rho G^dagger, and the diagonal count and
+  non-zero count whose per-step curves Sec. III-A plots.
 
 Precision: fp64 / complex128 everywhere.
 """
@@ -380,3 +385,49 @@ def fd_grad(psi0: np.ndarray, n: int, gates, terms, nparams: int, h: float = 1e-
                 minus.append(g)
         grad[j] = (energy(psi0, n, plus, terms) - energy(psi0, n, minus, terms)) / (2 * h)
     return grad
+
+
+# --------------------------------------------------------------------------
+# Matrix-level simulation (Sec. II-B; the Sec. III-A sparsity curves)
+# --------------------------------------------------------------------------
+
+def count_nonzeros(A: np.ndarray, tol: float = 0.0) -> int:
+    """Elements with |a| > tol (a != 0 when tol = 0)."""
+    return int(np.count_nonzero(np.abs(A) > tol)) if tol > 0 else int(np.count_nonzero(A))
+
+
+def count_diagonals(A: np.ndarray, tol: float = 0.0) -> int:
+    """Diagonals (dIndex = col - row) holding an element counted by
+    count_nonzeros."""
+    N = A.shape[0]
+    keep = (np.abs(A) > tol) if tol > 0 else (A != 0)
+    r, c = np.nonzero(keep)
+    return int(np.unique(c - r).size) if r.size else 0
+
+
+def unitary_chain(n: int, gates, tol: float = 0.0, start: np.ndarray | None = None):
+    """U_t = G_t U_{t-1} from U_0 = start (identity by default), G_t the
+    dense expanded time-step matrix of gate t.  Returns (U, records) with
+    records[t] = (diagonals, non-zeros) of U_t."""
+    U = np.eye(1 << n, dtype=np.complex128) if start is None else np.array(start, dtype=np.complex128)
+    rec = []
+    for g in gates:
+        U = dense_matrix(n, [g]) @ U
+        rec.append((count_diagonals(U, tol), count_nonzeros(U, tol)))
+    return U, rec
+
+
+def density_chain(rho: np.ndarray, n: int, gates, tol: float = 0.0):
+    """rho_t = G_t rho_{t-1} G_t^dagger, dense; returns (rho, records)."""
+    R = np.array(rho, dtype=np.complex128)
+    rec = []
+    for g in gates:
+        G = dense_matrix(n, [g])
+        R = G @ R @ G.conj().T
+        rec.append((count_diagonals(R, tol), count_nonzeros(R, tol)))
+    return R, rec
+
+
+def trace_product(A: np.ndarray, B: np.ndarray) -> complex:
+    """Tr(A B)."""
+    return complex(np.trace(A @ B))

@@ -330,6 +330,76 @@ def test_hh_is_identity(orc):
 
 
 # --------------------------------------------------------------------------
+# Matrix-level simulation: unitary chains and density matrices (Sec. II-B)
+# --------------------------------------------------------------------------
+
+def ghz_unitary(n):
+    """Closed form of the GHZ circuit's unitary: H on qubit 0 sends |j> to
+    (|j with bit 0 cleared> +- |j with bit 0 set>)/sqrt 2, and the CX ladder
+    then flips bits 1..n-1 of the second term."""
+    N = 1 << n
+    j = np.arange(N)
+    s = 1 / math.sqrt(2)
+    U = np.zeros((N, N), dtype=complex)
+    U[j & ~1, j] = s
+    U[(j | 1) ^ (N - 2), j] += np.where(j & 1, -s, s)
+    return U
+
+
+def test_unitary_chain_ghz10_stays_sparse(orc):
+    """Sec. III-A: the GHZ(10) unitary simulation stays at least 99.8 %
+    sparse at every time step; the final unitary is the closed form, 2048
+    non-zeros on 1025 diagonals."""
+    n = 10
+    U, rec = orc.unitary_chain(n, W.ghz(n))
+    assert np.max(np.abs(U - ghz_unitary(n))) < 1e-15
+    for nd, nnz in rec:
+        assert nnz == 2048 and 1 - nnz / 4 ** n >= 0.998
+    assert rec[-1] == (1025, 2048)
+
+
+def test_unitary_chain_order_and_counts(orc):
+    """Each new time step multiplies on the left (checked against products
+    of Kronecker-built matrices), and the counts follow closed forms: H on
+    every qubit is dense (4^n non-zeros on 2^(n+1) - 1 diagonals), X on every
+    qubit the anti-identity (2^n non-zeros on 2^n diagonals)."""
+    rng = np.random.default_rng(31)
+    n = 4
+    gates = [W.u3(*rng.uniform(0, 6, 3), 1), W.cx(0, 2), W.Gate("RY", (3,), (0,), (0.7,)), W.swap(1, 3), W.h(2)]
+    want = np.eye(1 << n, dtype=complex)
+    for g in gates:
+        want = pins.kron_expand(orc.gate_matrix(g.kind, g.params), g.targets, g.controls, n) @ want
+    U, _ = orc.unitary_chain(n, gates)
+    assert np.max(np.abs(U - want)) < 1e-14
+    n = 5
+    _, rec = orc.unitary_chain(n, [W.h(q) for q in range(n)])
+    assert rec[-1] == (2 ** (n + 1) - 1, 4 ** n)
+    _, rec = orc.unitary_chain(n, [W.Gate("X", (q,)) for q in range(n)])
+    assert rec[-1] == (2 ** n, 2 ** n)
+
+
+def test_density_chain_pure_and_mixed(orc):
+    """rho = |psi><psi| evolves into |U psi><U psi| (U psi from the
+    bit-manipulation state path); the maximally mixed state is invariant;
+    trace, Hermiticity and purity are kept, and Tr(H rho) is <U psi|H|U psi>."""
+    n = 5
+    gates = W.random_layered(n, 2, 7) + W.tfim(n, 2, 0.2)
+    psi = W.random_state(n, 3)
+    R, rec = orc.density_chain(np.outer(psi, psi.conj()), n, gates)
+    phi = orc.apply_circuit(psi, n, gates)
+    assert np.max(np.abs(R - np.outer(phi, phi.conj()))) < 1e-14
+    assert abs(np.trace(R) - 1) < 1e-14 and np.max(np.abs(R - R.conj().T)) < 1e-15
+    assert rec[-1] == (2 ** (n + 1) - 1, 4 ** n)
+    N = 1 << n
+    M, _ = orc.density_chain(np.eye(N) / N, n, gates)
+    assert np.max(np.abs(M - np.eye(N) / N)) < 1e-15
+    terms = W.tfim_terms(n)
+    H = pins.hamiltonian_dense(n, terms)
+    assert abs(orc.trace_product(H, R) - orc.expect(n, terms, phi)) < 1e-13
+    assert abs(orc.trace_product(R, R) - 1) < 1e-13
+
+
+# --------------------------------------------------------------------------
 # Observables
 # --------------------------------------------------------------------------
 
