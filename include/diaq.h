@@ -390,6 +390,55 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                  int32_t measure, diaq_plan_t* out);
 
 /* ------------------------------------------------------------------ */
+/* Matrix-level simulation (Sec. II-B): unitary simulation and          */
+/* density-matrix evolution, on DiaQ matrices through the Alg. 1 product */
+/* ------------------------------------------------------------------ */
+
+/* Per-gate record of a chained product, the quantities behind the
+ * sparsity and diagonal-count curves of Sec. III-A. */
+typedef struct diaq_chain_step {
+  int32_t ndiag;    /* stored diagonals after this time step */
+  int32_t reserved;
+  int64_t nnz;      /* stored elements with |v| > drop_tol (v != 0 if 0) */
+  int64_t nvalues;  /* stored elements: the DiaQ footprint in elements */
+} diaq_chain_step_t;
+
+/* Number of stored elements of A (its applied view's values) with
+ * |v| > tol, or v != 0 when tol = 0 (Sec. III-A sparsity = 1 - nnz / 4^n).
+ * Synchronises the stream.  tol < 0: DIAQ_ERR_INVALID_ARGUMENT. */
+diaq_status_t diaq_dia_nnz(diaq_ctx_t ctx, diaq_dia_t A, double tol, int64_t* nnz);
+
+/* out[0] + i out[1] = Tr(A B) = sum_d sum_i A[i, i+d] B[i+d, i], pairing A's
+ * diagonal d with B's diagonal -d (either operand may be a transposed or
+ * conjugated view).  Gives Tr(H rho) and the purity Tr(rho^2).  Summed per
+ * workgroup, then in a fixed order: repeat calls are bitwise equal.
+ * Dimension or dtype mismatch: DIAQ_ERR_NOT_MULTIPLYABLE.  Synchronises. */
+diaq_status_t diaq_trace_product(diaq_ctx_t ctx, diaq_dia_t A, diaq_dia_t B, double* out);
+
+/* Unitary simulation (Sec. II-B; Sec. III-A tracks its sparsity): the
+ * circuit's 2^n x 2^n unitary U = G_{ngates-1} ... G_0 * start, each G_t
+ * the expanded time-step matrix of gate t (Sec. II-C), multiplied in by
+ * Alg. 1 (diaq_fuse) one gate at a time.  start = NULL starts from the
+ * identity; start is not modified.  After each gate, diagonals whose values
+ * all have |v| <= drop_tol are dropped and, if steps != NULL, steps[t]
+ * receives the diagonal count and non-zeros.  The library allocates *out
+ * (free with diaq_dia_free).  n outside [1, 15]: DIAQ_ERR_UNSUPPORTED (the
+ * product can hold up to 2^(n+1) - 1 diagonals).  Invalid gate: the
+ * diaq_from_gate error, with nothing allocated.  Synchronises. */
+diaq_status_t diaq_unitary(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t ngates, int32_t nqubits,
+                           diaq_dtype_t dtype, diaq_dia_t start, double drop_tol, diaq_chain_step_t* steps,
+                           diaq_dia_t* out);
+
+/* Density-matrix evolution (Sec. II-B): rho <- G_t rho G_t^dagger for each
+ * gate in order, as two Alg. 1 products per gate, the right factor being
+ * G_t's transposed, conjugated view (a relabelling, Sec. IV).  rho is any
+ * DiaQ matrix of n <= 15 qubits (typically Hermitian, unit trace) and is
+ * not modified; *out is allocated by the library.  drop_tol and steps as
+ * for diaq_unitary.  Synchronises. */
+diaq_status_t diaq_density_evolve(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t ngates, diaq_dia_t rho,
+                                  double drop_tol, diaq_chain_step_t* steps, diaq_dia_t* out);
+
+/* ------------------------------------------------------------------ */
 /* Kernel timing (the counterpart of the simulator trace timer the paper
  * reads its times from, Sec. VII)                                      */
 /* ------------------------------------------------------------------ */

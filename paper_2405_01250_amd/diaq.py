@@ -59,6 +59,11 @@ class diaq_tuning_t(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 1)]
 
 
+class diaq_chain_step_t(ctypes.Structure):
+    _fields_ = [("ndiag", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("nvalues", ctypes.c_int64)]
+
+
 class diaq_profile_t(ctypes.Structure):
     _fields_ = [("expand_launches", ctypes.c_int64), ("expand_ms", ctypes.c_double),
                 ("expand_bytes", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
@@ -107,6 +112,12 @@ _SIGS = {
     "diaq_batch_free": [_P],
     "diaq_autotune": [_P, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(diaq_tuning_t)],
     "diaq_autotune_plan": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _I32, _I32, ctypes.POINTER(diaq_plan_t)],
+    "diaq_dia_nnz": [_P, _P, _D, ctypes.POINTER(_I64)],
+    "diaq_trace_product": [_P, _P, _P, ctypes.POINTER(_D)],
+    "diaq_unitary": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _P, _D, ctypes.POINTER(diaq_chain_step_t),
+                     ctypes.POINTER(_P)],
+    "diaq_density_evolve": [_P, ctypes.POINTER(diaq_gate_t), _I64, _P, _D, ctypes.POINTER(diaq_chain_step_t),
+                            ctypes.POINTER(_P)],
     "diaq_profile_start": [_P],
     "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
@@ -331,6 +342,27 @@ def from_dense_diagonals(n: int, diags: dict, dtype=torch.complex128, ctx: Conte
     t = torch.from_numpy(np.ascontiguousarray(packed.astype(np.complex128 if dtype == torch.complex128
                                                             else np.complex64))).to("cuda")
     return dia_create(n, offs, t if t.numel() else None, dtype, ctx)
+
+
+def from_dense(A: np.ndarray, dtype=torch.complex128, ctx: Context | None = None) -> DiaqMatrix:
+    """numpy dense -> DiaQ converter: the diagonals holding a non-zero."""
+    A = np.asarray(A)
+    N = A.shape[0]
+    if A.shape != (N, N) or N & (N - 1) or N < 2:
+        raise ValueError("need a square 2^n x 2^n matrix")
+    diags = {d: np.diagonal(A, d) for d in range(-(N - 1), N) if np.any(np.diagonal(A, d) != 0)}
+    return from_dense_diagonals(N.bit_length() - 1, diags, dtype, ctx)
+
+
+def to_dense(M: DiaqMatrix) -> np.ndarray:
+    """DiaQ -> numpy dense converter (host copy of the applied matrix)."""
+    n, _, dt, _, _ = M.info()
+    N = 1 << n
+    A = np.zeros((N, N), dtype=np.complex128 if dt == C128 else np.complex64)
+    for d, v in M.diagonals().items():
+        t = np.arange(N - abs(d))
+        A[t + max(0, -d), t + max(0, d)] = v
+    return A
 
 
 def from_gate_query(gate, n: int):
@@ -610,3 +642,52 @@ def autotune_plan(gates: Sequence, n: int, dtype=torch.complex128, allow_kron: b
     _check(load().diaq_autotune_plan(ctx.handle, arr, len(gates), n, _dtype_code(dtype), int(allow_kron), measure,
                                      ctypes.byref(p)))
     return p
+
+
+# --------------------------------------------------------------------------
+# Matrix-level simulation: unitary and density-matrix evolution
+# --------------------------------------------------------------------------
+
+def dia_nnz(A: DiaqMatrix, tol: float = 0.0) -> int:
+    """Stored elements with |v| > tol (v != 0 when tol = 0)."""
+    out = _I64()
+    _check(load().diaq_dia_nnz(A.ctx.handle, A.handle, float(tol), ctypes.byref(out)))
+    return out.value
+
+
+def trace_product(A: DiaqMatrix, B: DiaqMatrix) -> complex:
+    """Tr(A B) (e.g. Tr(H rho), or the purity Tr(rho rho))."""
+    out = (_D * 2)()
+    _check(load().diaq_trace_product(A.ctx.handle, A.handle, B.handle, out))
+    return complex(out[0], out[1])
+
+
+def _steps_array(steps, count: int) -> np.ndarray:
+    rec = np.zeros(count, dtype=[("ndiag", np.int32), ("nnz", np.int64), ("nvalues", np.int64)])
+    for t in range(count):
+        rec[t] = (steps[t].ndiag, steps[t].nnz, steps[t].nvalues)
+    return rec
+
+
+def unitary(gates: Sequence, n: int, dtype=torch.complex128, start: DiaqMatrix | None = None,
+            drop_tol: float = 0.0, track: bool = True, ctx: Context | None = None):
+    """Unitary simulation: (U, per-gate records of ndiag / nnz / nvalues)
+    with U = G_last ... G_first * start (identity when start is None)."""
+    ctx = ctx or context()
+    arr, keep = gate_array(gates)
+    steps = (diaq_chain_step_t * max(1, len(gates)))() if track else None
+    h = _P()
+    _check(load().diaq_unitary(ctx.handle, arr, len(gates), n, _dtype_code(dtype),
+                               start.handle if start is not None else None, float(drop_tol), steps,
+                               ctypes.byref(h)))
+    return DiaqMatrix(h, ctx), (_steps_array(steps, len(gates)) if track else None)
+
+
+def density_evolve(gates: Sequence, rho: DiaqMatrix, drop_tol: float = 0.0, track: bool = True):
+    """rho <- G rho G^dagger for each gate: (rho_out, per-gate records)."""
+    arr, keep = gate_array(gates)
+    steps = (diaq_chain_step_t * max(1, len(gates)))() if track else None
+    h = _P()
+    _check(load().diaq_density_evolve(rho.ctx.handle, arr, len(gates), rho.handle, float(drop_tol), steps,
+                                      ctypes.byref(h)))
+    return DiaqMatrix(h, rho.ctx), (_steps_array(steps, len(gates)) if track else None)
