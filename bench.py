@@ -229,6 +229,7 @@ def main():
                                       {"kron": True}, {"kron": True, "fuse": True, "max_fused_qubits": 2},
                                       {"kron": True, "fuse": True, "max_fused_qubits": 3})]
         out["tfim"] = tfim_extra(D, W, torch, ctx, state, scratch, tdt)
+        out["matrix"] = matrix_extra(D, W)
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
         out["batch"] = batch_extra(D, W, torch, dev)
     if a.cpu_seconds > 0:
@@ -297,6 +298,39 @@ def tfim_extra(D, W, torch, ctx, state, scratch, tdt):
     out["magnetization"] = mags[0]
     out["max_magnetization_diff"] = max(abs(m - mags[0]) for m in mags)
     return out
+
+
+def matrix_extra(D, W):
+    """Matrix-level simulation through chained Alg. 1 products: the circuit
+    unitary of GHZ, TFIM and QFT circuits with the per-step diagonal count
+    and sparsity, and density-matrix evolution of a pure TFIM state."""
+    import numpy as np
+    rows = []
+    for name, n, gates in [("GHZ", 10, W.ghz(10)), ("GHZ", 14, W.ghz(14)), ("TFIM", 10, W.tfim(10, 2, 0.1)),
+                           ("QFT", 10, W.qft(10)), ("QFT", 12, W.qft(12))]:
+        N = 1 << n
+        t0 = time.perf_counter()
+        U, rec = D.unitary(gates, n)
+        dt = time.perf_counter() - t0
+        rows.append({"unitary": "%s-%d" % (name, n), "gates": len(gates), "ms": round(dt * 1e3, 2),
+                     "ms_per_gate": round(dt * 1e3 / len(gates), 3), "final_ndiag": int(rec[-1]["ndiag"]),
+                     "final_nnz": int(rec[-1]["nnz"]), "min_sparsity": round(float(1 - rec["nnz"].max() / N ** 2), 6),
+                     "diaq_stored_values": int(rec[-1]["nvalues"]), "dense_values": N * N})
+        del U
+    n = 8
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0] = 1
+    rho = D.from_dense(np.outer(psi, psi))
+    gates = W.tfim(n, 3, 0.1)
+    t0 = time.perf_counter()
+    R, rec = D.density_evolve(gates, rho, drop_tol=1e-14)
+    dt = time.perf_counter() - t0
+    I = D.from_dense(np.eye(1 << n))
+    M = D.from_pauli_sum(n, W.magnetization_terms(n))
+    rows.append({"density": "TFIM-%d, 3 steps, |0..0><0..0|" % n, "gates": len(gates), "ms": round(dt * 1e3, 2),
+                 "final_ndiag": int(rec[-1]["ndiag"]), "trace": D.trace_product(I, R).real,
+                 "purity": D.trace_product(R, R).real, "magnetization": D.trace_product(M, R).real})
+    return rows
 
 
 def batch_extra(D, W, torch, dev, reps=3):
