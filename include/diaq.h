@@ -390,7 +390,7 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                  int32_t measure, diaq_plan_t* out);
 
 /* ------------------------------------------------------------------ */
-/* Matrix-level simulation (Sec. II-B): unitary simulation and          */
+/* Matrix-level simulation (Sec. II-A): unitary simulation and          */
 /* density-matrix evolution, on DiaQ matrices through the Alg. 1 product */
 /* ------------------------------------------------------------------ */
 
@@ -415,7 +415,7 @@ diaq_status_t diaq_dia_nnz(diaq_ctx_t ctx, diaq_dia_t A, double tol, int64_t* nn
  * Dimension or dtype mismatch: DIAQ_ERR_NOT_MULTIPLYABLE.  Synchronises. */
 diaq_status_t diaq_trace_product(diaq_ctx_t ctx, diaq_dia_t A, diaq_dia_t B, double* out);
 
-/* Unitary simulation (Sec. II-B; Sec. III-A tracks its sparsity): the
+/* Unitary simulation (Sec. II-A; Sec. III-A tracks its sparsity): the
  * circuit's 2^n x 2^n unitary U = G_{ngates-1} ... G_0 * start, each G_t
  * the expanded time-step matrix of gate t (Sec. II-C), multiplied in by
  * Alg. 1 (diaq_fuse) one gate at a time.  start = NULL starts from the
@@ -429,7 +429,7 @@ diaq_status_t diaq_unitary(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t nga
                            diaq_dtype_t dtype, diaq_dia_t start, double drop_tol, diaq_chain_step_t* steps,
                            diaq_dia_t* out);
 
-/* Density-matrix evolution (Sec. II-B): rho <- G_t rho G_t^dagger for each
+/* Density-matrix evolution (Sec. II-A): rho <- G_t rho G_t^dagger for each
  * gate in order, as two Alg. 1 products per gate, the right factor being
  * G_t's transposed, conjugated view (a relabelling, Sec. IV).  rho is any
  * DiaQ matrix of n <= 15 qubits (typically Hermitian, unit trace) and is

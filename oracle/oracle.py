@@ -23,7 +23,7 @@ What each function follows
   parameter-shift rule and by central differences.
 * ``unitary_chain`` / ``density_chain`` / ``count_diagonals`` /
   ``count_nonzeros`` / ``trace_product`` -- matrix-level simulation
-  (Sec. II-B): the circuit unitary as the running dense product of the
+  (Sec. II-A): the circuit unitary as the running dense product of the
   time-step matrices, rho <- G rho G^dagger, and the diagonal count and
   non-zero count whose per-step curves Sec. III-A plots.
 
@@ -388,7 +388,7 @@ def fd_grad(psi0: np.ndarray, n: int, gates, terms, nparams: int, h: float = 1e-
 
 
 # --------------------------------------------------------------------------
-# Matrix-level simulation (Sec. II-B; the Sec. III-A sparsity curves)
+# Matrix-level simulation (Sec. II-A; the Sec. III-A sparsity curves)
 # --------------------------------------------------------------------------
 
 def count_nonzeros(A: np.ndarray, tol: float = 0.0) -> int:

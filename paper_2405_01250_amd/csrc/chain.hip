@@ -1,7 +1,7 @@
 // chain.hip -- matrix-level simulation on DiaQ matrices: unitary simulation
-// (the product of all time-step unitaries of a circuit, Sec. II-B, with the
+// (the product of all time-step unitaries of a circuit, Sec. II-A, with the
 // per-step diagonal count and sparsity the paper tracks in Sec. III-A) and
-// density-matrix evolution rho <- G rho G^dagger (Sec. II-B), both built
+// density-matrix evolution rho <- G rho G^dagger (Sec. II-A), both built
 // from the Alg. 1 product (fuse_dia) and the free transpose of Sec. IV.
 //
 // Also: the number of stored non-zeros of a DiaQ matrix, and Tr(A B)

@@ -330,7 +330,7 @@ def test_hh_is_identity(orc):
 
 
 # --------------------------------------------------------------------------
-# Matrix-level simulation: unitary chains and density matrices (Sec. II-B)
+# Matrix-level simulation: unitary chains and density matrices (Sec. II-A)
 # --------------------------------------------------------------------------
 
 def ghz_unitary(n):
