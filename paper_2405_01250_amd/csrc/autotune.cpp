@@ -258,7 +258,7 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
     };
     std::vector<Cand> cands;
     // measured-or-nominal rates (GB/s) for the byte model
-    const double rate_dia = 5900.0, rate_kron = 6200.0, launch_ms = 0.004;
+    const double rate_dia = 6000.0, rate_kron = 5700.0, launch_ms = 0.004;
     auto add = [&](int fuse, int k, int kron) -> diaq_status_t {
       diaq_plan_t p{};
       p.fuse = fuse;
@@ -279,7 +279,7 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       for (const auto& op : ops) {
         const double E = double(packing_starts(gate_offsets(op.core), n).back());
         if (kron) {
-          bytes += 2 * s * N;
+          bytes += kron_op_bytes(op.core, int(op.post.size()), n, dtype);
         } else {
           bytes += s * (2 * E + 2 * N);
           maxb = std::max(maxb, s * E);

@@ -164,12 +164,11 @@ diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, di
   DiagFactor* dtab = nullptr;
   std::vector<size_t> first;
   DIAQ_TRY(upload_factors(ctx, ops, &dtab, &first));
-  const double bytes = 2.0 * double(elem_bytes(dt)) * double(int64_t(1) << n);
   for (size_t k = 0; k < ops.size(); k++) {
     const int nf = int(ops[k].post.size());
     const size_t e0 = prof_mark(ctx);
     DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false, nf ? dtab + first[k] : nullptr, nf));
-    prof_interval(ctx, e0, prof_mark(ctx), 1, bytes);
+    prof_interval(ctx, e0, prof_mark(ctx), 1, kron_op_bytes(ops[k].core, nf, n, dt));
   }
   return DIAQ_OK;
 }
@@ -249,12 +248,13 @@ diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates, int32_t 
         DIAQ_TRY(plan_fusion(gates, ngates, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2, dtype,
                              &ops, true));
         count = int64_t(ops.size());
+        for (const auto& op : ops) b += kron_op_bytes(op.core, int(op.post.size()), nqubits, dtype);
       } else {
         Prepared p;
         DIAQ_TRY(prepare_gates(gates, ngates, nqubits, &p));
         count = ngates;
+        for (const auto& lg : p.lg) b += kron_op_bytes(lg, 0, nqubits, dtype);
       }
-      b = double(count) * 2.0 * s * N;  // each op reads and writes the state once
     } else if (plan && plan->fuse) {
       std::vector<FusedOp> ops;
       DIAQ_TRY(plan_fusion(gates, ngates, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2, dtype,

@@ -219,6 +219,11 @@ diaq_status_t launch_kron_adjoint(diaq_ctx* ctx, hipStream_t stream, const Local
                                   int n, diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back,
                                   const double* dmat = nullptr);
 // spmv.hip: one workgroup sums partial[0..count) into dres (2 doubles).
+// Algorithmic bytes of one Alg. 3 operation: every amplitude it changes is
+// read and written once.  Without folded factors only the rows whose
+// controls are all 1 change (1 / 2^nc of the state); folded factors touch
+// every row.
+double kron_op_bytes(const LocalGate& core, int nf, int n, diaq_dtype_t dt);
 diaq_status_t launch_final_reduce(hipStream_t stream, const double2* partial, int64_t count, double* dres);
 
 // fuse.hip

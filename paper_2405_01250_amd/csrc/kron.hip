@@ -18,7 +18,9 @@ namespace diaq {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kCosetsPerLane = 2;
+// One coset per lane and a full grid: in-place streams run faster with
+// more workgroups in flight than with several cosets per lane.
+constexpr int kCosetsPerLane = 1;
 
 template <typename R>
 struct Vec;
@@ -154,9 +156,11 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
   using V = typename Vec<R>::V;
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
+    const bool on = (uint64_t(i) & a.cmask) == a.cmask;
+    if (!on && a.nf == 0) continue;  // an unfolded controlled phase leaves these rows alone
     V t = v[i];
     double tr = double(t.x), ti = double(t.y);
-    if ((uint64_t(i) & a.cmask) == a.cmask) {
+    if (on) {
       int r = 0;
       for (int j = 0; j < a.k; j++)
         if ((i & a.off[1 << j]) != 0) r |= 1 << j;
@@ -275,7 +279,7 @@ template <typename R, bool DM>
 void dispatch_apply(const KronArgs& a, int k, bool diag, int64_t N, int num_cus, hipStream_t stream, void* v) {
   using V = typename Vec<R>::V;
   if (diag) {
-    const int64_t blocks = std::min<int64_t>((N + kBlock - 1) / kBlock, int64_t(num_cus) * 32);
+    const int64_t blocks = (N + kBlock - 1) / kBlock;
     hipLaunchKernelGGL((kron_diag_kernel<R, DM>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, a, N,
                        static_cast<V*>(v));
     return;
@@ -307,6 +311,11 @@ void dispatch_adjoint(const KronArgs& a, int k, int64_t blocks, hipStream_t stre
 }
 
 }  // namespace
+
+double kron_op_bytes(const LocalGate& core, int nf, int n, diaq_dtype_t dt) {
+  const double full = 2.0 * double(elem_bytes(dt)) * double(int64_t(1) << n);
+  return nf ? full : full / double(int64_t(1) << core.nc);
+}
 
 diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
                                 void* v, bool adjoint, const DiagFactor* factors, int nf, const double* dmat) {

@@ -515,7 +515,7 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
     // only a principal-diagonal-only matrix may run in place
     if (!(op.nd == 1 && op.host_off[0] == 0))
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "x and y alias for a matrix with off-principal diagonals");
-    const int64_t blocks = std::min<int64_t>((N + kBlock - 1) / kBlock, int64_t(ctx->num_cus) * 64);
+    const int64_t blocks = (N + kBlock - 1) / kBlock;  // one element per lane
     if (op.dtype == DIAQ_C128)
       hipLaunchKernelGGL(diag_inplace_kernel<double>, dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream, N,
                          op.conjugate ? 1 : 0, static_cast<const double2*>(op.values), static_cast<double2*>(y));
