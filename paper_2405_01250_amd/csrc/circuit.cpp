@@ -310,20 +310,40 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
                     gates[g].kind);
       diff[g] = 1;
     }
-    // device slots: [0] = <psi|H|psi>, [1 + g] = <lam|G_g|psi>
-    DIAQ_TRY(ensure(ctx, &ctx->aux, size_t(ngates + 1) * 2 * sizeof(double) + 256));
-    double* dots = static_cast<double*>(ctx->aux.ptr);
-    DIAQ_HIP(hipMemsetAsync(dots, 0, size_t(ngates + 1) * 2 * sizeof(double), ctx->stream));
-
     const bool kron = plan && plan->kron;
-    // forward: psi = U psi0
+    // forward: psi = U psi0 (Alg. 3 plan: fused in-place operations)
     DIAQ_HIP(hipMemcpyAsync(psi, psi0, vb, hipMemcpyDeviceToDevice, ctx->stream));
     if (kron) {
-      DIAQ_TRY(run_kron(ctx, unfused_ops(p), nqubits, dtype, psi));
+      std::vector<FusedOp> ops;
+      const int kmax = plan->max_fused_qubits > 0 ? std::min(plan->max_fused_qubits, 3) : 3;
+      DIAQ_TRY(plan_fusion(gates, ngates, nqubits, kmax, dtype, &ops, true));
+      DIAQ_TRY(run_kron(ctx, ops, nqubits, dtype, psi));
     } else {
       void* res = nullptr;
       DIAQ_TRY(run_plain(ctx, p, 0, ngates, nqubits, dtype, psi, tmp, &res));
       if (res != psi) std::swap(psi, tmp);
+    }
+    // Alg. 3 reverse sweep: segments of gates per pass (n >= 3)
+    const bool segmented = kron && nqubits >= 3;
+    SegmentPlan sp;
+    std::vector<char> table;
+    if (segmented) {
+      DIAQ_TRY(plan_segments(p.lg, gens, diff, nqubits, &sp));
+      std::vector<int64_t> slots(sp.dot_gate.size());
+      for (size_t j = 0; j < slots.size(); j++) slots[j] = sp.dot_gate[j] + 1;
+      segment_table_host(sp, table, slots);
+    }
+    // device slots: [0] = <psi|H|psi>, [1 + g] = <lam|G_g|psi>; the segment
+    // table follows
+    const size_t dots_bytes = ((size_t(ngates + 1) * 2 * sizeof(double) + 255) / 256) * 256;
+    DIAQ_TRY(ensure(ctx, &ctx->aux, dots_bytes + table.size() + 256));
+    double* dots = static_cast<double*>(ctx->aux.ptr);
+    char* dtable = static_cast<char*>(ctx->aux.ptr) + dots_bytes;
+    DIAQ_HIP(hipMemsetAsync(dots, 0, size_t(ngates + 1) * 2 * sizeof(double), ctx->stream));
+    if (!table.empty()) {
+      // synchronous: the host image dies with this call
+      DIAQ_HIP(hipStreamSynchronize(ctx->stream));
+      DIAQ_HIP(hipMemcpy(dtable, table.data(), table.size(), hipMemcpyHostToDevice));
     }
     // lam = H psi ; E = <psi|lam>
     DIAQ_TRY(launch_spmv(ctx, op_of(H, H->transposed, H->conjugated), psi, lam));
@@ -335,7 +355,11 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     ident.m[1][1][0] = 1;
     DIAQ_TRY(launch_generator_dot(ctx, ident, nqubits, dtype, psi, lam, dots));
     // reverse sweep
-    if (kron) {
+    if (segmented) {
+      DIAQ_TRY(ensure(ctx, &ctx->red, size_t(segment_blocks(nqubits)) * kSegMaxDots * sizeof(double2)));
+      DIAQ_TRY(run_segments(ctx, ctx->stream, sp, nqubits, dtype, psi, lam, dtable,
+                            static_cast<double2*>(ctx->red.ptr), dots));
+    } else if (kron) {
       // one fused Alg. 3 pass per gate: generator dot, then psi, lam <- U^dagger
       int64_t maxb = 1;
       for (int64_t g = 0; g < ngates; g++) maxb = std::max(maxb, kron_adjoint_blocks(p.lg[g], nqubits));

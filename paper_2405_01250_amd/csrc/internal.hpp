@@ -224,6 +224,57 @@ diaq_status_t launch_kron_adjoint(diaq_ctx* ctx, hipStream_t stream, const Local
 // controls are all 1 change (1 / 2^nc of the state); folded factors touch
 // every row.
 double kron_op_bytes(const LocalGate& core, int nf, int n, diaq_dtype_t dt);
+// ---------------------------------------------------------------------------
+// Segmented adjoint sweep (segment.hip)
+// ---------------------------------------------------------------------------
+
+// One gate of a segment in the coset's local basis (bit j of a local index
+// is qubit S[j], S ascending).
+struct SegGate {
+  int32_t kind;     // 0: one target, 1: two targets, 2: three targets (= S), 3: diagonal
+  int32_t b0, b1;   // local bits of targets 0 and 1 (kinds 0, 1)
+  int32_t dot;      // slot of this gate's dot within the segment, -1 if none
+  int32_t dk;       // diagonal: number of qubits in q
+  int32_t q[3];     // diagonal: the gate's qubits, q[0] = bit 0 of its table
+  uint64_t cmask;   // controls: the gate acts where all are 1
+  int64_t moff;     // doubles into the pool: U^dagger, then the generator
+};
+
+struct Segment {
+  int S[3];            // coset qubits, ascending
+  int64_t first = 0;   // first SegGate
+  int64_t ngates = 0;
+  int32_t ndots = 0;
+  int64_t dot_slot0 = 0;  // first entry of SegmentPlan::dot_gate
+};
+
+struct SegmentPlan {
+  std::vector<SegGate> gates;    // all segments, each in reverse circuit order
+  std::vector<double> pool;      // matrices
+  std::vector<Segment> segs;     // in sweep order (last gates first)
+  std::vector<int64_t> dot_gate; // circuit gate index of each dot, by segment
+};
+
+constexpr int kSegMaxDots = 64;
+constexpr int kSegMaxGates = 512;
+
+// Cut the reverse sweep into segments: consecutive gates whose non-diagonal
+// targets fit in 3 qubits (diagonal gates and controls anywhere).  diff[g]
+// marks gates whose dot is wanted; gens[g] is then their generator.
+diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<LocalGate>& gens,
+                            const std::vector<int>& diff, int n, SegmentPlan* out);
+// Device table layout [gates | pool | dot output slots]: its size, and its
+// host image with slots[j] = output slot (pairs of doubles) of dot j.
+size_t segment_table_bytes(const SegmentPlan& P);
+void segment_table_host(const SegmentPlan& P, std::vector<char>& host, const std::vector<int64_t>& slots);
+int64_t segment_blocks(int n);
+// Run the sweep: for every segment one pass over psi and lambda (each dot
+// taken before its gate is undone), then the fixed-order dot sums into
+// dots[2 * slot], dots[2 * slot + 1].  partial holds segment_blocks(n) *
+// kSegMaxDots entries.
+diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan& P, int n, diaq_dtype_t dt,
+                           void* psi, void* lam, void* table_mem, double2* partial, double* dots);
+
 diaq_status_t launch_final_reduce(hipStream_t stream, const double2* partial, int64_t count, double* dres);
 
 // fuse.hip

@@ -1,0 +1,465 @@
+// segment.hip -- the adjoint reverse sweep with many gates per pass.
+//
+// The reverse sweep needs, for every differentiable gate g (in reverse
+// order), the dot <lambda|G_g|psi> at the point right after g, and then
+// psi, lambda <- U_g^dagger (the transpose-and-conjugate of Sec. IV).  Done
+// gate by gate that is four vector streams per gate.  Here the sweep is cut
+// into segments of consecutive gates whose non-diagonal targets fit in three
+// qubits S; diagonal gates (and the controls of any gate) may sit on any
+// qubit.  One lane owns a coset of S (8 amplitudes of psi and of lambda, the
+// cosets of Alg. 3) and replays the segment's gates on it in exact reverse
+// order, taking each gate's dot before undoing it.  Every amplitude of psi
+// and lambda is then read and written once per segment instead of once per
+// gate, and nothing is reordered, so the result is the gate-by-gate sweep
+// up to rounding.
+//
+// Dots: each wave reduces its lanes' contributions with shuffles and parks
+// the sum in LDS; the workgroup writes one partial per dot, and a second
+// kernel sums the partials over workgroups in a fixed order.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace diaq {
+
+namespace {
+
+constexpr int kSegBlock = 256;
+constexpr int kSegWaves = kSegBlock / 64;
+
+enum SegKind : int32_t { kOne = 0, kTwo = 1, kThree = 2, kDiag = 3 };
+
+struct SegArgs {
+  int64_t ncos;        // N / 8
+  int32_t sorted[3];   // S ascending
+  int32_t ngates;
+  int32_t ndots;
+  int32_t pad;
+  int64_t off[8];      // global offset of local index r
+  const SegGate* gates;
+  const double* pool;
+};
+
+template <typename R>
+struct Vec;
+template <>
+struct Vec<double> {
+  using V = double2;
+};
+template <>
+struct Vec<float> {
+  using V = float2;
+};
+
+struct Coset {
+  double pr[8], pi[8], lr[8], li[8];
+};
+
+// y = M x on the local indices idx[0..D) of the coset, for psi and lambda,
+// after the dot conj(lambda) (G psi) when G != nullptr.
+template <int D>
+__device__ __forceinline__ void local_apply(Coset& s, const int (&idx)[D], const double* __restrict__ m,
+                                            const double* __restrict__ g, double& dre, double& dim) {
+  if (g) {
+#pragma unroll
+    for (int r = 0; r < D; r++) {
+      double gr = 0, gi = 0;
+#pragma unroll
+      for (int c = 0; c < D; c++) {
+        const double a = g[(r * D + c) * 2], b = g[(r * D + c) * 2 + 1];
+        gr += a * s.pr[idx[c]] - b * s.pi[idx[c]];
+        gi += a * s.pi[idx[c]] + b * s.pr[idx[c]];
+      }
+      dre += s.lr[idx[r]] * gr + s.li[idx[r]] * gi;
+      dim += s.lr[idx[r]] * gi - s.li[idx[r]] * gr;
+    }
+  }
+  double yr[D], yi[D], zr[D], zi[D];
+#pragma unroll
+  for (int r = 0; r < D; r++) {
+    double ar = 0, ai = 0, br = 0, bi = 0;
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+      const double a = m[(r * D + c) * 2], b = m[(r * D + c) * 2 + 1];
+      ar += a * s.pr[idx[c]] - b * s.pi[idx[c]];
+      ai += a * s.pi[idx[c]] + b * s.pr[idx[c]];
+      br += a * s.lr[idx[c]] - b * s.li[idx[c]];
+      bi += a * s.li[idx[c]] + b * s.lr[idx[c]];
+    }
+    yr[r] = ar;
+    yi[r] = ai;
+    zr[r] = br;
+    zi[r] = bi;
+  }
+#pragma unroll
+  for (int r = 0; r < D; r++) {
+    s.pr[idx[r]] = yr[r];
+    s.pi[idx[r]] = yi[r];
+    s.lr[idx[r]] = zr[r];
+    s.li[idx[r]] = zi[r];
+  }
+}
+
+// One-target gate on local bit B: four pairs (r, r | 1 << B).
+template <int B>
+__device__ __forceinline__ void apply_one(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
+                                          double& dim) {
+  const double* m = a.pool + sg.moff;
+  const double* g = sg.dot >= 0 ? m + 8 : nullptr;
+#pragma unroll
+  for (int p = 0; p < 4; p++) {
+    const int r0 = ((p >> B) << (B + 1)) | (p & ((1 << B) - 1));
+    const int idx[2] = {r0, r0 | (1 << B)};
+    if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
+    local_apply<2>(s, idx, m, g, dre, dim);
+  }
+}
+
+// Two-target gate: target 0 on local bit B0, target 1 on B1; two quads.
+template <int B0, int B1>
+__device__ __forceinline__ void apply_two(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
+                                          double& dim) {
+  constexpr int FREE = 7 & ~((1 << B0) | (1 << B1));
+  const double* m = a.pool + sg.moff;
+  const double* g = sg.dot >= 0 ? m + 32 : nullptr;
+#pragma unroll
+  for (int p = 0; p < 2; p++) {
+    const int r0 = p ? FREE : 0;
+    const int idx[4] = {r0, r0 | (1 << B0), r0 | (1 << B1), r0 | (1 << B0) | (1 << B1)};
+    if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
+    local_apply<4>(s, idx, m, g, dre, dim);
+  }
+}
+
+__device__ __forceinline__ void apply_three(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base,
+                                            double& dre, double& dim) {
+  if (sg.cmask && ((uint64_t(base) & sg.cmask) != sg.cmask)) return;
+  const double* m = a.pool + sg.moff;
+  const double* g = sg.dot >= 0 ? m + 128 : nullptr;
+  const int idx[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+  local_apply<8>(s, idx, m, g, dre, dim);
+}
+
+__device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
+                                           double& dim) {
+  const double* v = a.pool + sg.moff;
+  const double* g = v + 2 * (1 << sg.dk);
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    const uint64_t i = uint64_t(base + a.off[r]);
+    if ((i & sg.cmask) != sg.cmask) continue;
+    int t = 0;
+    for (int j = 0; j < sg.dk; j++) t |= int((i >> sg.q[j]) & 1) << j;
+    if (sg.dot >= 0) {
+      const double gr = g[2 * t] * s.pr[r] - g[2 * t + 1] * s.pi[r];
+      const double gi = g[2 * t] * s.pi[r] + g[2 * t + 1] * s.pr[r];
+      dre += s.lr[r] * gr + s.li[r] * gi;
+      dim += s.lr[r] * gi - s.li[r] * gr;
+    }
+    const double vr = v[2 * t], vi = v[2 * t + 1];
+    double x = vr * s.pr[r] - vi * s.pi[r];
+    s.pi[r] = vr * s.pi[r] + vi * s.pr[r];
+    s.pr[r] = x;
+    x = vr * s.lr[r] - vi * s.li[r];
+    s.li[r] = vr * s.li[r] + vi * s.lr[r];
+    s.lr[r] = x;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSegBlock) void segment_adjoint_kernel(SegArgs a, typename Vec<R>::V* __restrict__ psi,
+                                                                    typename Vec<R>::V* __restrict__ lam,
+                                                                    double2* __restrict__ partial) {
+  using V = typename Vec<R>::V;
+  __shared__ double2 acc[kSegMaxDots][kSegWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t c = int64_t(blockIdx.x) * kSegBlock + threadIdx.x;
+  const bool live = c < a.ncos;
+  int64_t base = 0;
+  if (live) {
+    base = c;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      const int p = a.sorted[j];
+      base = (base & ((int64_t(1) << p) - 1)) | ((base >> p) << (p + 1));
+    }
+  }
+  Coset s;
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    V x = live ? psi[base + a.off[r]] : V{0, 0};
+    V y = live ? lam[base + a.off[r]] : V{0, 0};
+    s.pr[r] = double(x.x);
+    s.pi[r] = double(x.y);
+    s.lr[r] = double(y.x);
+    s.li[r] = double(y.y);
+  }
+  for (int gi = 0; gi < a.ngates; gi++) {
+    const SegGate sg = a.gates[gi];
+    double dre = 0, dim = 0;
+    if (live) {
+      switch (sg.kind) {
+        case kOne:
+          if (sg.b0 == 0) apply_one<0>(s, a, sg, base, dre, dim);
+          else if (sg.b0 == 1) apply_one<1>(s, a, sg, base, dre, dim);
+          else apply_one<2>(s, a, sg, base, dre, dim);
+          break;
+        case kTwo: {
+          const int code = sg.b0 * 3 + sg.b1;
+          switch (code) {
+            case 1: apply_two<0, 1>(s, a, sg, base, dre, dim); break;
+            case 2: apply_two<0, 2>(s, a, sg, base, dre, dim); break;
+            case 3: apply_two<1, 0>(s, a, sg, base, dre, dim); break;
+            case 5: apply_two<1, 2>(s, a, sg, base, dre, dim); break;
+            case 6: apply_two<2, 0>(s, a, sg, base, dre, dim); break;
+            default: apply_two<2, 1>(s, a, sg, base, dre, dim); break;
+          }
+          break;
+        }
+        case kThree:
+          apply_three(s, a, sg, base, dre, dim);
+          break;
+        default:
+          apply_diag(s, a, sg, base, dre, dim);
+          break;
+      }
+    }
+    if (sg.dot >= 0) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        dre += __shfl_xor(dre, o, 64);
+        dim += __shfl_xor(dim, o, 64);
+      }
+      if (lane == 0) acc[sg.dot][wave] = double2{dre, dim};
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+      psi[base + a.off[r]] = V{R(s.pr[r]), R(s.pi[r])};
+      lam[base + a.off[r]] = V{R(s.lr[r]), R(s.li[r])};
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < a.ndots; j += kSegBlock) {
+    double2 t = acc[j][0];
+    for (int w = 1; w < kSegWaves; w++) {
+      t.x += acc[j][w].x;
+      t.y += acc[j][w].y;
+    }
+    partial[int64_t(blockIdx.x) * a.ndots + j] = t;
+  }
+}
+
+// Dot j of a segment: the partials of all workgroups summed in a fixed
+// order, written to out[2 * slot[j]].
+__global__ __launch_bounds__(256) void segment_reduce_kernel(const double2* __restrict__ partial, int64_t blocks,
+                                                             int32_t ndots, const int64_t* __restrict__ slot,
+                                                             double* __restrict__ out) {
+  const int j = blockIdx.x;
+  double re = 0, im = 0;
+  for (int64_t b = threadIdx.x; b < blocks; b += 256) {
+    re += partial[b * ndots + j].x;
+    im += partial[b * ndots + j].y;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  __shared__ double2 ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = double2{re, im};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 t = ws[0];
+    for (int w = 1; w < 4; w++) {
+      t.x += ws[w].x;
+      t.y += ws[w].y;
+    }
+    out[2 * slot[j]] = t.x;
+    out[2 * slot[j] + 1] = t.y;
+  }
+}
+
+bool is_diag(const LocalGate& lg) {
+  const int d = 1 << lg.k;
+  for (int r = 0; r < d; r++)
+    for (int c = 0; c < d; c++)
+      if (r != c && lg.structural[r][c]) return false;
+  return true;
+}
+
+// Padding qubits for a segment whose non-diagonal targets use fewer than
+// three: middle qubits first (measured the best-coalesced cosets), then
+// the rest.
+void pad_set(std::vector<int>& S, int n) {
+  std::vector<int> order;
+  for (int q = std::min(10, n - 1); q < n; q++) order.push_back(q);
+  for (int q = std::min(10, n - 1) - 1; q >= 0; q--) order.push_back(q);
+  for (int q : order) {
+    if (int(S.size()) == 3) break;
+    if (std::find(S.begin(), S.end(), q) == S.end()) S.push_back(q);
+  }
+  std::sort(S.begin(), S.end());
+}
+
+int local_bit(const std::vector<int>& S, int q) {
+  return int(std::find(S.begin(), S.end(), q) - S.begin());
+}
+
+}  // namespace
+
+diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<LocalGate>& gens,
+                            const std::vector<int>& diff, int n, SegmentPlan* out) {
+  if (n < 3) return fail(DIAQ_ERR_UNSUPPORTED, "segment sweep needs n >= 3");
+  SegmentPlan& P = *out;
+  P = SegmentPlan();
+  const int64_t G = int64_t(lg.size());
+  int64_t g = G - 1;
+  while (g >= 0) {
+    // grow the segment backwards from gate g
+    std::vector<int> S;
+    std::vector<int64_t> members;
+    int ndots = 0;
+    for (; g >= 0; g--) {
+      const LocalGate& L = lg[size_t(g)];
+      std::vector<int> T;
+      if (!is_diag(L))
+        for (int j = 0; j < L.k; j++) T.push_back(L.targets[j]);
+      std::vector<int> U = S;
+      for (int q : T)
+        if (std::find(U.begin(), U.end(), q) == U.end()) U.push_back(q);
+      if (U.size() > 3 || int(members.size()) >= kSegMaxGates || (diff[size_t(g)] && ndots >= kSegMaxDots)) break;
+      S = U;
+      members.push_back(g);
+      if (diff[size_t(g)]) ndots++;
+    }
+    pad_set(S, n);
+    Segment seg;
+    for (int j = 0; j < 3; j++) seg.S[j] = S[size_t(j)];
+    seg.first = int64_t(P.gates.size());
+    seg.ndots = 0;
+    seg.dot_slot0 = int64_t(P.dot_gate.size());
+    for (int64_t m : members) {
+      const LocalGate& L = lg[size_t(m)];
+      SegGate sg;
+      std::memset(&sg, 0, sizeof(sg));
+      sg.cmask = L.cmask;
+      sg.dot = diff[size_t(m)] ? seg.ndots++ : -1;
+      if (sg.dot >= 0) P.dot_gate.push_back(m);
+      sg.moff = int64_t(P.pool.size());
+      const int d = 1 << L.k;
+      auto push = [&](double re, double im) {
+        P.pool.push_back(re);
+        P.pool.push_back(im);
+      };
+      if (is_diag(L)) {
+        sg.kind = kDiag;
+        sg.dk = L.k;
+        for (int j = 0; j < L.k; j++) sg.q[j] = L.targets[j];
+        for (int r = 0; r < d; r++) push(L.m[r][r][0], -L.m[r][r][1]);  // U^dagger
+        if (sg.dot >= 0)
+          for (int r = 0; r < d; r++) push(gens[size_t(m)].m[r][r][0], gens[size_t(m)].m[r][r][1]);
+      } else {
+        // local order: kOne / kTwo keep the gate's own order (b0, b1 say where
+        // its targets sit in S); kThree is permuted into S's order
+        int perm[8];
+        for (int r = 0; r < d; r++) perm[r] = r;
+        if (L.k == 1) {
+          sg.kind = kOne;
+          sg.b0 = local_bit(S, L.targets[0]);
+        } else if (L.k == 2) {
+          sg.kind = kTwo;
+          sg.b0 = local_bit(S, L.targets[0]);
+          sg.b1 = local_bit(S, L.targets[1]);
+        } else {
+          sg.kind = kThree;
+          // S-local index rs -> gate-local index
+          for (int rs = 0; rs < 8; rs++) {
+            int rg = 0;
+            for (int j = 0; j < 3; j++)
+              if ((rs >> j) & 1) rg |= 1 << (std::find(L.targets, L.targets + 3, S[size_t(j)]) - L.targets);
+            perm[rs] = rg;
+          }
+        }
+        for (int r = 0; r < d; r++)
+          for (int c = 0; c < d; c++) {
+            const int pr = perm[r], pc = perm[c];
+            push(L.m[pc][pr][0], -L.m[pc][pr][1]);  // U^dagger[r][c] = conj(U[c][r])
+          }
+        if (sg.dot >= 0)
+          for (int r = 0; r < d; r++)
+            for (int c = 0; c < d; c++) push(gens[size_t(m)].m[perm[r]][perm[c]][0],
+                                              gens[size_t(m)].m[perm[r]][perm[c]][1]);
+      }
+      P.gates.push_back(sg);
+    }
+    seg.ngates = int64_t(P.gates.size()) - seg.first;
+    P.segs.push_back(seg);
+  }
+  return DIAQ_OK;
+}
+
+diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan& P, int n, diaq_dtype_t dt,
+                           void* psi, void* lam, void* table_mem, double2* partial, double* dots) {
+  // table_mem: device copy of [gates | pool | dot slots], laid out by segment_table_bytes
+  char* t = static_cast<char*>(table_mem);
+  const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
+  const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
+  const SegGate* dg = reinterpret_cast<const SegGate*>(t);
+  const double* dp = reinterpret_cast<const double*>(t + gb);
+  const int64_t* ds = reinterpret_cast<const int64_t*>(t + gb + pb);
+  const int64_t ncos = (int64_t(1) << n) >> 3;
+  const int64_t blocks = (ncos + kSegBlock - 1) / kSegBlock;
+  for (const Segment& seg : P.segs) {
+    SegArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ncos = ncos;
+    for (int j = 0; j < 3; j++) a.sorted[j] = seg.S[j];
+    for (int r = 0; r < 8; r++) {
+      int64_t o = 0;
+      for (int j = 0; j < 3; j++)
+        if ((r >> j) & 1) o |= int64_t(1) << seg.S[j];
+      a.off[r] = o;
+    }
+    a.ngates = int32_t(seg.ngates);
+    a.ndots = seg.ndots;
+    a.gates = dg + seg.first;
+    a.pool = dp;
+    if (dt == DIAQ_C128)
+      hipLaunchKernelGGL(segment_adjoint_kernel<double>, dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+                         static_cast<double2*>(psi), static_cast<double2*>(lam), partial);
+    else
+      hipLaunchKernelGGL(segment_adjoint_kernel<float>, dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+                         static_cast<float2*>(psi), static_cast<float2*>(lam), partial);
+    DIAQ_HIP(hipGetLastError());
+    if (seg.ndots) {
+      hipLaunchKernelGGL(segment_reduce_kernel, dim3(unsigned(seg.ndots)), dim3(256), 0, stream, partial, blocks,
+                         seg.ndots, ds + seg.dot_slot0, dots);
+      DIAQ_HIP(hipGetLastError());
+    }
+  }
+  return DIAQ_OK;
+}
+
+size_t segment_table_bytes(const SegmentPlan& P) {
+  const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
+  const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
+  return gb + pb + P.dot_gate.size() * sizeof(int64_t) + 256;
+}
+
+void segment_table_host(const SegmentPlan& P, std::vector<char>& host, const std::vector<int64_t>& slots) {
+  const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
+  const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
+  host.assign(segment_table_bytes(P), 0);
+  if (!P.gates.empty()) std::memcpy(host.data(), P.gates.data(), P.gates.size() * sizeof(SegGate));
+  if (!P.pool.empty()) std::memcpy(host.data() + gb, P.pool.data(), P.pool.size() * sizeof(double));
+  if (!slots.empty()) std::memcpy(host.data() + gb + pb, slots.data(), slots.size() * sizeof(int64_t));
+}
+
+int64_t segment_blocks(int n) {
+  const int64_t ncos = (int64_t(1) << n) >> 3;
+  return (ncos + kSegBlock - 1) / kSegBlock;
+}
+
+}  // namespace diaq

@@ -1,0 +1,118 @@
+"""The segmented Alg. 3 reverse sweep of diaq_adjoint_grad (several gates
+per pass over psi and lambda): random circuits with every gate shape the
+segments distinguish (one, two and three targets, diagonal gates anywhere,
+controls inside and outside the coset qubits, shared parameters), against
+the oracle's energy and central differences, and against the gate-by-gate
+plain path."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2405_01250_amd import diaq as D
+from paper_2405_01250_amd import inputs as W
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+ROT1 = ["RX", "RY", "RZ", "P"]
+ROT2 = ["RXX", "RYY", "RZZ"]
+
+
+def _circuit(rng, n, ngates, nparams):
+    gates = []
+    for _ in range(ngates):
+        qs = [int(q) for q in rng.permutation(n)]
+        r = rng.random()
+        if r < 0.35:
+            kind = ROT1[int(rng.integers(len(ROT1)))] if n < 2 or rng.random() < 0.6 else ROT2[int(rng.integers(3))]
+            nt = 2 if kind in ROT2 else 1
+            nc = int(rng.integers(0, min(2, n - nt) + 1)) if rng.random() < 0.3 else 0
+            gates.append(W.Gate(kind, tuple(qs[:nt]), tuple(qs[nt:nt + nc]), (float(rng.uniform(0, 6)),),
+                                int(rng.integers(nparams)), float(rng.uniform(0.5, 1.5))))
+        elif r < 0.55:
+            gates.append(W.u3(*rng.uniform(0, 6, 3), qs[0]))
+        elif r < 0.65 and n >= 2:
+            gates.append(W.cx(qs[0], qs[1]))
+        elif r < 0.72 and n >= 3:
+            gates.append(W.Gate("X", (qs[0],), (qs[1], qs[2])))
+        elif r < 0.8 and n >= 2:
+            gates.append(W.swap(qs[0], qs[1]))
+        elif r < 0.9 and n >= 3:
+            k = int(rng.integers(2, 4))
+            m = rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+            q, _ = np.linalg.qr(m)
+            nc = int(rng.integers(0, min(1, n - k) + 1))
+            gates.append(W.Gate("MATRIX", tuple(qs[:k]), tuple(qs[k:k + nc]), matrix=q))
+        else:
+            gates.append(W.Gate(["Z", "S", "T"][int(rng.integers(3))], (qs[0],),
+                                tuple(qs[1:1 + int(rng.integers(0, min(2, n - 1) + 1))])))
+    return gates
+
+
+def _terms(rng, n, count=6):
+    return [(int(rng.integers(0, 1 << n)), int(rng.integers(0, 1 << n)), float(rng.standard_normal()))
+            for _ in range(count)]
+
+
+@pytest.mark.parametrize("n,seed", [(3, 1), (4, 2), (5, 3), (7, 4), (9, 5), (12, 6)])
+def test_segmented_sweep_matches_plain_and_fd(n, seed):
+    rng = np.random.default_rng(seed)
+    nparams = 6
+    gates = _circuit(rng, n, 40, nparams)
+    terms = _terms(rng, n)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = W.random_state(n, seed)
+    e_k, g_k = D.adjoint_grad(gates, H, to_dev(psi0), nparams, plan=D.make_plan(kron=True))
+    e_p, g_p = D.adjoint_grad(gates, H, to_dev(psi0), nparams)
+    assert abs(e_k - orc.energy(psi0, n, gates, terms)) <= 1e-12
+    assert np.max(np.abs(g_k - g_p)) <= 1e-11 * max(1.0, np.max(np.abs(g_p)))
+    if n <= 7:
+        fd = orc.fd_grad(psi0, n, gates, terms, nparams, h=1e-4)
+        assert np.max(np.abs(g_k - fd)) <= 1e-7 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_segmented_sweep_many_dots_in_one_segment():
+    """More differentiable diagonal gates than one segment holds: the sweep
+    must split and still match parameter shift."""
+    n = 6
+    rng = np.random.default_rng(11)
+    gates, pidx = [], 0
+    for _ in range(3):
+        for q in range(n):
+            gates.append(W.Gate("RY", (q,), (), (float(rng.uniform(0, 6)),), pidx, 1.0))
+            pidx += 1
+        for _ in range(30):
+            a, b = rng.permutation(n)[:2]
+            gates.append(W.Gate("RZZ", (int(a), int(b)), (), (float(rng.uniform(0, 6)),), pidx, 1.0))
+            pidx += 1
+    terms = [(0, 3, 0.7), (1 << 2, 0, -0.4), (0b110, 0b011, 0.25)]
+    H = D.from_pauli_sum(n, terms)
+    psi0 = W.zero_state(n)
+    e, g = D.adjoint_grad(gates, H, to_dev(psi0), pidx, plan=D.make_plan(kron=True))
+    ps = orc.param_shift_grad(psi0, n, gates, terms, pidx)
+    assert abs(e - orc.energy(psi0, n, gates, terms)) <= 1e-12
+    assert np.max(np.abs(g - ps)) <= 1e-10 * max(1.0, np.max(np.abs(ps)))
+
+
+@pytest.mark.parametrize("n,layers", [(10, 3), (16, 2), (20, 8)])
+def test_segmented_hea_and_qaoa(n, layers):
+    gates, theta, terms = W.hea(n, layers, 60 + n)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = to_dev(W.zero_state(n))
+    e_k, g_k = D.adjoint_grad(gates, H, psi0, len(theta), plan=D.make_plan(kron=True))
+    e_p, g_p = D.adjoint_grad(gates, H, psi0, len(theta))
+    assert abs(e_k - e_p) <= 1e-12
+    assert np.max(np.abs(g_k - g_p)) <= 1e-11
+    rng = np.random.default_rng(n)
+    edges = W.random_regular3(n if n % 2 == 0 else n + 1, rng)
+    edges = [(a, b) for a, b in edges if a < n and b < n]
+    gam, bet = rng.uniform(0, math.pi, 2), rng.uniform(0, math.pi, 2)
+    qg = W.qaoa_gates(n, edges, gam, bet)
+    C = D.from_pauli_sum(n, W.maxcut_terms(edges))
+    e_k, g_k = D.adjoint_grad(qg, C, psi0, 4, plan=D.make_plan(kron=True))
+    e_p, g_p = D.adjoint_grad(qg, C, psi0, 4)
+    assert abs(e_k - e_p) <= 1e-11 and np.max(np.abs(g_k - g_p)) <= 1e-10
