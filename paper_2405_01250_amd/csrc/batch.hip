@@ -414,7 +414,49 @@ struct WideCirc {
   int64_t dot0 = 0;  // first dot slot
   std::vector<LocalGate> lg, gen;
   std::vector<int32_t> pidx, rot;
+  std::vector<double> angle0;  // each gate's own angle (params[0])
+  std::vector<double> scale;
+  SegmentPlan fwd, rev;        // forward pass and reverse sweep, several gates per pass
+  size_t o_fwd = 0, o_rev = 0; // their device tables, offsets into the batch block
+  void* d_fwd = nullptr;
+  void* d_rev = nullptr;
 };
+
+// A rotation whose matrix sits in a segment table: rewritten from the angle
+// before each run (the angle from theta, or the gate's own angle).
+struct SegPatch {
+  double* dst;
+  int32_t rot;
+  int32_t diag;    // 1: the table holds the diagonal only
+  int32_t dim;     // 2 or 4
+  int32_t dagger;  // 1: store U^dagger (reverse sweep)
+  int64_t slot;    // theta index
+  double scale;
+  double angle0;
+};
+
+__global__ void seg_patch_kernel(const SegPatch* __restrict__ patches, int64_t count,
+                                 const double* __restrict__ theta) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const SegPatch p = patches[i];
+  double m[4][4][2];
+  rot_matrix(p.rot, theta ? p.scale * theta[p.slot] : p.angle0, m);
+  const double sg = p.dagger ? -1.0 : 1.0;
+  if (p.diag) {
+    for (int r = 0; r < p.dim; r++) {
+      p.dst[2 * r] = m[r][r][0];
+      p.dst[2 * r + 1] = sg * m[r][r][1];
+    }
+  } else {
+    for (int r = 0; r < p.dim; r++)
+      for (int c = 0; c < p.dim; c++) {
+        const int rr = p.dagger ? c : r, cc = p.dagger ? r : c;
+        p.dst[2 * (r * p.dim + c)] = m[rr][cc][0];
+        p.dst[2 * (r * p.dim + c) + 1] = sg * m[rr][cc][1];
+      }
+  }
+}
 
 }  // namespace
 }  // namespace diaq
@@ -438,6 +480,8 @@ struct diaq_batch {
   double2* d_dots = nullptr;
   double2* d_evals = nullptr;
   double2* d_partial[diaq::kWideStreams] = {};
+  diaq::SegPatch* d_patch = nullptr;
+  int64_t npatch = 0;
   double* pinned = nullptr;      // theta in, expvals + grads out
   int64_t pinned_theta = 0, pinned_out = 0;
   size_t lds_bytes = 0;
@@ -451,37 +495,22 @@ struct diaq_batch {
 namespace diaq {
 namespace {
 
-diaq_status_t enqueue_wide(diaq_batch* b, const WideCirc& w, hipStream_t s, bool use_theta) {
+diaq_status_t enqueue_wide(diaq_batch* b, const WideCirc& w, hipStream_t s) {
   diaq_ctx* ctx = b->ctx;
   const int64_t N = int64_t(1) << w.n;
   double2* psi = b->ws + w.s0;
   double2* lam = psi + N;
   double2* part = b->d_partial[w.slot];
-  const int64_t ib = std::min<int64_t>((N + 255) / 256, int64_t(ctx->num_cus) * 16);
-  hipLaunchKernelGGL(wide_init_kernel, dim3(unsigned(ib)), dim3(256), 0, s, psi, N);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, psi, N);
   DIAQ_HIP(hipGetLastError());
-  auto dmat = [&](size_t j) -> const double* {
-    return (use_theta && w.pidx[j] >= 0 && w.rot[j] != kFixed) ? b->args.mats + (w.g0 + int64_t(j)) * 32 : nullptr;
-  };
-  for (size_t j = 0; j < w.lg.size(); j++)
-    DIAQ_TRY(launch_kron_apply(ctx, s, w.lg[j], w.n, DIAQ_C128, psi, false, nullptr, 0, dmat(j)));
+  DIAQ_TRY(run_segments(ctx, s, w.fwd, w.n, DIAQ_C128, psi, nullptr, w.d_fwd, nullptr, nullptr));
   const int64_t ob = (N + kObsBlock - 1) / kObsBlock;
   hipLaunchKernelGGL(wide_observable_kernel, dim3(unsigned(ob)), dim3(kObsBlock), 0, s, psi, lam, N,
                      b->args.zmask + w.t0, b->args.coef + w.t0, w.nt, part);
   DIAQ_HIP(hipGetLastError());
   const int64_t wi = &w - b->wide.data();
   DIAQ_TRY(launch_final_reduce(s, part, ob, reinterpret_cast<double*>(b->d_evals + wi)));
-  int64_t slot = w.dot0;
-  for (int64_t j = int64_t(w.lg.size()) - 1; j >= 0; j--) {
-    const bool diff = w.pidx[j] >= 0;
-    if (!diff && j == 0) break;
-    DIAQ_TRY(launch_kron_adjoint(ctx, s, w.lg[j], diff ? &w.gen[j] : nullptr, w.n, DIAQ_C128, psi, lam, part, j > 0,
-                                 dmat(size_t(j))));
-    if (diff) {
-      DIAQ_TRY(launch_final_reduce(s, part, kron_adjoint_blocks(w.lg[j], w.n), reinterpret_cast<double*>(b->d_dots + slot)));
-      slot++;
-    }
-  }
+  DIAQ_TRY(run_segments(ctx, s, w.rev, w.n, DIAQ_C128, psi, lam, w.d_rev, part, reinterpret_cast<double*>(b->d_dots)));
   return DIAQ_OK;
 }
 
@@ -501,6 +530,11 @@ diaq_status_t enqueue(diaq_batch* b, bool use_theta) {
                      args.expvals, int64_t(b->ncirc), args.grads, b->nparams);
   DIAQ_HIP(hipGetLastError());
   const bool wide = !b->wide.empty();
+  if (b->npatch) {
+    hipLaunchKernelGGL(seg_patch_kernel, dim3(unsigned((b->npatch + 255) / 256)), dim3(256), 0, b->stream, b->d_patch,
+                       b->npatch, use_theta ? args.theta : nullptr);
+    DIAQ_HIP(hipGetLastError());
+  }
   if (wide) {
     DIAQ_HIP(hipEventRecord(b->fork, b->stream));
     for (int j = 0; j < kWideStreams; j++) DIAQ_HIP(hipStreamWaitEvent(b->side[j], b->fork, 0));
@@ -510,7 +544,7 @@ diaq_status_t enqueue(diaq_batch* b, bool use_theta) {
     DIAQ_HIP(hipGetLastError());
   }
   if (wide) {
-    for (const auto& w : b->wide) DIAQ_TRY(enqueue_wide(b, w, b->side[w.slot], use_theta));
+    for (const auto& w : b->wide) DIAQ_TRY(enqueue_wide(b, w, b->side[w.slot]));
     for (int j = 0; j < kWideStreams; j++) {
       DIAQ_HIP(hipEventRecord(b->join[j], b->side[j]));
       DIAQ_HIP(hipStreamWaitEvent(b->stream, b->join[j], 0));
@@ -650,6 +684,8 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
           wc.gen.push_back(gen);
           wc.pidx.push_back(bg.pidx);
           wc.rot.push_back(bg.rot);
+          wc.angle0.push_back(g->params[0]);
+          wc.scale.push_back(g->param_scale);
         }
       }
       work[c] = double(int64_t(1) << C.nqubits) * double(3 * C.ngates + 1);
@@ -686,9 +722,25 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
       }
     }
     int64_t maxpart = 1;
-    for (const auto& w : wide) {
+    size_t seg_bytes = 0;
+    std::vector<std::vector<char>> seg_host;
+    for (auto& w : wide) {
       maxpart = std::max<int64_t>(maxpart, ((int64_t(1) << w.n) + kObsBlock - 1) / kObsBlock);
-      for (const auto& lg : w.lg) maxpart = std::max<int64_t>(maxpart, kron_adjoint_blocks(lg, w.n));
+      maxpart = std::max<int64_t>(maxpart, segment_blocks(w.n) * kSegMaxDots);
+      std::vector<int> diff(w.lg.size());
+      for (size_t j = 0; j < w.lg.size(); j++) diff[j] = w.pidx[j] >= 0 ? 1 : 0;
+      DIAQ_TRY(plan_segments(w.lg, w.gen, diff, w.n, &w.fwd, true));
+      DIAQ_TRY(plan_segments(w.lg, w.gen, diff, w.n, &w.rev, false));
+      std::vector<int64_t> slots(w.rev.dot_gate.size());
+      for (size_t j = 0; j < slots.size(); j++) slots[j] = w.dot0 + int64_t(j);
+      seg_host.emplace_back();
+      segment_table_host(w.fwd, seg_host.back(), {});
+      w.o_fwd = seg_bytes;
+      seg_bytes += (seg_host.back().size() + 255) / 256 * 256;
+      seg_host.emplace_back();
+      segment_table_host(w.rev, seg_host.back(), slots);
+      w.o_rev = seg_bytes;
+      seg_bytes += (seg_host.back().size() + 255) / 256 * 256;
     }
 
     diaq_batch* b = new diaq_batch();
@@ -727,6 +779,29 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     const size_t o_dots = off; off += al(wmeta.size() * sizeof(double2) + 1);
     const size_t o_evals = off; off += al(wide.size() * sizeof(double2) + 1);
     const size_t o_part = off; off += al(size_t(maxpart) * sizeof(double2)) * kWideStreams;
+    const size_t o_seg = off; off += al(seg_bytes + 1);
+    // matrices of rotations inside the segment tables
+    std::vector<SegPatch> patches;
+    for (const auto& w : wide)
+      for (const SegmentPlan* P : {&w.fwd, &w.rev})
+        for (size_t i = 0; i < P->gates.size(); i++) {
+          const int64_t m = P->gate_of[i];
+          if (w.pidx[size_t(m)] < 0 || w.rot[size_t(m)] == kFixed) continue;
+          SegPatch sp;
+          std::memset(&sp, 0, sizeof(sp));
+          sp.rot = w.rot[size_t(m)];
+          sp.diag = P->gates[i].kind == 3 ? 1 : 0;
+          sp.dim = sp.diag ? (1 << P->gates[i].dk) : (P->gates[i].kind == 0 ? 2 : 4);
+          sp.dagger = P->forward ? 0 : 1;
+          sp.slot = circ[size_t(w.c)].p0 + w.pidx[size_t(m)];
+          sp.scale = w.scale[size_t(m)];
+          sp.angle0 = w.angle0[size_t(m)];
+          // device address, filled in below: table offset + pool offset + moff
+          sp.dst = reinterpret_cast<double*>(
+              (P == &w.fwd ? w.o_fwd : w.o_rev) + segment_pool_offset(*P) + size_t(P->gates[i].moff) * sizeof(double));
+          patches.push_back(sp);
+        }
+    const size_t o_patch = off; off += al(patches.size() * sizeof(SegPatch) + 1);
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
       (void)hipGetLastError();
       return bail(fail(DIAQ_ERR_OUT_OF_MEMORY, "batch tables: %zu bytes", off));
@@ -747,6 +822,14 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     up(o_order, narrow.data(), narrow.size() * sizeof(int32_t));
     up(o_wres, wres.data(), wres.size() * sizeof(WideRes));
     up(o_wmeta, wmeta.data(), wmeta.size() * sizeof(WideDot));
+    for (size_t x = 0; x < wide.size(); x++) {
+      up(o_seg + wide[x].o_fwd, seg_host[2 * x].data(), seg_host[2 * x].size());
+      up(o_seg + wide[x].o_rev, seg_host[2 * x + 1].data(), seg_host[2 * x + 1].size());
+      wide[x].d_fwd = base + o_seg + wide[x].o_fwd;
+      wide[x].d_rev = base + o_seg + wide[x].o_rev;
+    }
+    for (auto& sp : patches) sp.dst = reinterpret_cast<double*>(base + o_seg + reinterpret_cast<size_t>(sp.dst));
+    up(o_patch, patches.data(), patches.size() * sizeof(SegPatch));
     if (e != hipSuccess) return bail(fail(DIAQ_ERR_DEVICE, "batch upload: %s", hipGetErrorString(e)));
     b->args.circ = reinterpret_cast<const BCirc*>(base + o_circ);
     b->args.gates = reinterpret_cast<const BGate*>(base + o_gates);
@@ -764,6 +847,8 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     b->d_wmeta = reinterpret_cast<WideDot*>(base + o_wmeta);
     b->d_dots = reinterpret_cast<double2*>(base + o_dots);
     b->d_evals = reinterpret_cast<double2*>(base + o_evals);
+    b->d_patch = reinterpret_cast<SegPatch*>(base + o_patch);
+    b->npatch = int64_t(patches.size());
     for (int j = 0; j < kWideStreams; j++)
       b->d_partial[j] = reinterpret_cast<double2*>(base + o_part + size_t(j) * al(size_t(maxpart) * sizeof(double2)));
     b->ngates = int64_t(gates.size());

@@ -249,7 +249,9 @@ struct Segment {
 };
 
 struct SegmentPlan {
-  std::vector<SegGate> gates;    // all segments, each in reverse circuit order
+  bool forward = false;          // circuit order with U (no dots) instead of the reverse sweep
+  std::vector<SegGate> gates;    // all segments, each in sweep order
+  std::vector<int64_t> gate_of;  // circuit gate index of each SegGate
   std::vector<double> pool;      // matrices
   std::vector<Segment> segs;     // in sweep order (last gates first)
   std::vector<int64_t> dot_gate; // circuit gate index of each dot, by segment
@@ -258,20 +260,24 @@ struct SegmentPlan {
 constexpr int kSegMaxDots = 64;
 constexpr int kSegMaxGates = 512;
 
-// Cut the reverse sweep into segments: consecutive gates whose non-diagonal
-// targets fit in 3 qubits (diagonal gates and controls anywhere).  diff[g]
-// marks gates whose dot is wanted; gens[g] is then their generator.
+// Cut the reverse sweep (or, with forward, the circuit in its own order)
+// into segments: consecutive gates whose non-diagonal targets fit in 3
+// qubits (diagonal gates and controls anywhere).  diff[g] marks gates whose
+// dot the reverse sweep takes; gens[g] is then their generator.
 diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<LocalGate>& gens,
-                            const std::vector<int>& diff, int n, SegmentPlan* out);
+                            const std::vector<int>& diff, int n, SegmentPlan* out, bool forward = false);
 // Device table layout [gates | pool | dot output slots]: its size, and its
 // host image with slots[j] = output slot (pairs of doubles) of dot j.
 size_t segment_table_bytes(const SegmentPlan& P);
 void segment_table_host(const SegmentPlan& P, std::vector<char>& host, const std::vector<int64_t>& slots);
 int64_t segment_blocks(int n);
+// Byte offset of the matrix pool inside the device table.
+size_t segment_pool_offset(const SegmentPlan& P);
 // Run the sweep: for every segment one pass over psi and lambda (each dot
 // taken before its gate is undone), then the fixed-order dot sums into
 // dots[2 * slot], dots[2 * slot + 1].  partial holds segment_blocks(n) *
-// kSegMaxDots entries.
+// kSegMaxDots entries.  A forward plan passes over psi alone (lam,
+// partial and dots unused).
 diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan& P, int n, diaq_dtype_t dt,
                            void* psi, void* lam, void* table_mem, double2* partial, double* dots);
 

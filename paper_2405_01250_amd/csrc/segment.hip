@@ -16,6 +16,11 @@
 // Dots: each wave reduces its lanes' contributions with shuffles and parks
 // the sum in LDS; the workgroup writes one partial per dot, and a second
 // kernel sums the partials over workgroups in a fixed order.
+//
+// A forward plan is the same cut taken in circuit order with U instead of
+// U^dagger and psi alone: the batched path uses it so that one table of
+// per-gate matrices (refreshed on the device from new angles) serves both
+// passes.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -57,10 +62,10 @@ struct Coset {
 
 // y = M x on the local indices idx[0..D) of the coset, for psi and lambda,
 // after the dot conj(lambda) (G psi) when G != nullptr.
-template <int D>
+template <int D, bool LAM>
 __device__ __forceinline__ void local_apply(Coset& s, const int (&idx)[D], const double* __restrict__ m,
                                             const double* __restrict__ g, double& dre, double& dim) {
-  if (g) {
+  if (LAM && g) {
 #pragma unroll
     for (int r = 0; r < D; r++) {
       double gr = 0, gi = 0;
@@ -83,8 +88,10 @@ __device__ __forceinline__ void local_apply(Coset& s, const int (&idx)[D], const
       const double a = m[(r * D + c) * 2], b = m[(r * D + c) * 2 + 1];
       ar += a * s.pr[idx[c]] - b * s.pi[idx[c]];
       ai += a * s.pi[idx[c]] + b * s.pr[idx[c]];
-      br += a * s.lr[idx[c]] - b * s.li[idx[c]];
-      bi += a * s.li[idx[c]] + b * s.lr[idx[c]];
+      if (LAM) {
+        br += a * s.lr[idx[c]] - b * s.li[idx[c]];
+        bi += a * s.li[idx[c]] + b * s.lr[idx[c]];
+      }
     }
     yr[r] = ar;
     yi[r] = ai;
@@ -95,13 +102,15 @@ __device__ __forceinline__ void local_apply(Coset& s, const int (&idx)[D], const
   for (int r = 0; r < D; r++) {
     s.pr[idx[r]] = yr[r];
     s.pi[idx[r]] = yi[r];
-    s.lr[idx[r]] = zr[r];
-    s.li[idx[r]] = zi[r];
+    if (LAM) {
+      s.lr[idx[r]] = zr[r];
+      s.li[idx[r]] = zi[r];
+    }
   }
 }
 
 // One-target gate on local bit B: four pairs (r, r | 1 << B).
-template <int B>
+template <int B, bool LAM>
 __device__ __forceinline__ void apply_one(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
                                           double& dim) {
   const double* m = a.pool + sg.moff;
@@ -111,12 +120,12 @@ __device__ __forceinline__ void apply_one(Coset& s, const SegArgs& a, const SegG
     const int r0 = ((p >> B) << (B + 1)) | (p & ((1 << B) - 1));
     const int idx[2] = {r0, r0 | (1 << B)};
     if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
-    local_apply<2>(s, idx, m, g, dre, dim);
+    local_apply<2, LAM>(s, idx, m, g, dre, dim);
   }
 }
 
 // Two-target gate: target 0 on local bit B0, target 1 on B1; two quads.
-template <int B0, int B1>
+template <int B0, int B1, bool LAM>
 __device__ __forceinline__ void apply_two(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
                                           double& dim) {
   constexpr int FREE = 7 & ~((1 << B0) | (1 << B1));
@@ -127,19 +136,21 @@ __device__ __forceinline__ void apply_two(Coset& s, const SegArgs& a, const SegG
     const int r0 = p ? FREE : 0;
     const int idx[4] = {r0, r0 | (1 << B0), r0 | (1 << B1), r0 | (1 << B0) | (1 << B1)};
     if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
-    local_apply<4>(s, idx, m, g, dre, dim);
+    local_apply<4, LAM>(s, idx, m, g, dre, dim);
   }
 }
 
+template <bool LAM>
 __device__ __forceinline__ void apply_three(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base,
                                             double& dre, double& dim) {
   if (sg.cmask && ((uint64_t(base) & sg.cmask) != sg.cmask)) return;
   const double* m = a.pool + sg.moff;
   const double* g = sg.dot >= 0 ? m + 128 : nullptr;
   const int idx[8] = {0, 1, 2, 3, 4, 5, 6, 7};
-  local_apply<8>(s, idx, m, g, dre, dim);
+  local_apply<8, LAM>(s, idx, m, g, dre, dim);
 }
 
+template <bool LAM>
 __device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
                                            double& dim) {
   const double* v = a.pool + sg.moff;
@@ -150,7 +161,7 @@ __device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const Seg
     if ((i & sg.cmask) != sg.cmask) continue;
     int t = 0;
     for (int j = 0; j < sg.dk; j++) t |= int((i >> sg.q[j]) & 1) << j;
-    if (sg.dot >= 0) {
+    if (LAM && sg.dot >= 0) {
       const double gr = g[2 * t] * s.pr[r] - g[2 * t + 1] * s.pi[r];
       const double gi = g[2 * t] * s.pi[r] + g[2 * t + 1] * s.pr[r];
       dre += s.lr[r] * gr + s.li[r] * gi;
@@ -160,14 +171,16 @@ __device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const Seg
     double x = vr * s.pr[r] - vi * s.pi[r];
     s.pi[r] = vr * s.pi[r] + vi * s.pr[r];
     s.pr[r] = x;
-    x = vr * s.lr[r] - vi * s.li[r];
-    s.li[r] = vr * s.li[r] + vi * s.lr[r];
-    s.lr[r] = x;
+    if (LAM) {
+      x = vr * s.lr[r] - vi * s.li[r];
+      s.li[r] = vr * s.li[r] + vi * s.lr[r];
+      s.lr[r] = x;
+    }
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(kSegBlock) void segment_adjoint_kernel(SegArgs a, typename Vec<R>::V* __restrict__ psi,
+template <typename R, bool LAM>
+__global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename Vec<R>::V* __restrict__ psi,
                                                                     typename Vec<R>::V* __restrict__ lam,
                                                                     double2* __restrict__ partial) {
   using V = typename Vec<R>::V;
@@ -188,7 +201,7 @@ __global__ __launch_bounds__(kSegBlock) void segment_adjoint_kernel(SegArgs a, t
 #pragma unroll
   for (int r = 0; r < 8; r++) {
     V x = live ? psi[base + a.off[r]] : V{0, 0};
-    V y = live ? lam[base + a.off[r]] : V{0, 0};
+    V y = (LAM && live) ? lam[base + a.off[r]] : V{0, 0};
     s.pr[r] = double(x.x);
     s.pi[r] = double(x.y);
     s.lr[r] = double(y.x);
@@ -200,31 +213,31 @@ __global__ __launch_bounds__(kSegBlock) void segment_adjoint_kernel(SegArgs a, t
     if (live) {
       switch (sg.kind) {
         case kOne:
-          if (sg.b0 == 0) apply_one<0>(s, a, sg, base, dre, dim);
-          else if (sg.b0 == 1) apply_one<1>(s, a, sg, base, dre, dim);
-          else apply_one<2>(s, a, sg, base, dre, dim);
+          if (sg.b0 == 0) apply_one<0, LAM>(s, a, sg, base, dre, dim);
+          else if (sg.b0 == 1) apply_one<1, LAM>(s, a, sg, base, dre, dim);
+          else apply_one<2, LAM>(s, a, sg, base, dre, dim);
           break;
         case kTwo: {
           const int code = sg.b0 * 3 + sg.b1;
           switch (code) {
-            case 1: apply_two<0, 1>(s, a, sg, base, dre, dim); break;
-            case 2: apply_two<0, 2>(s, a, sg, base, dre, dim); break;
-            case 3: apply_two<1, 0>(s, a, sg, base, dre, dim); break;
-            case 5: apply_two<1, 2>(s, a, sg, base, dre, dim); break;
-            case 6: apply_two<2, 0>(s, a, sg, base, dre, dim); break;
-            default: apply_two<2, 1>(s, a, sg, base, dre, dim); break;
+            case 1: apply_two<0, 1, LAM>(s, a, sg, base, dre, dim); break;
+            case 2: apply_two<0, 2, LAM>(s, a, sg, base, dre, dim); break;
+            case 3: apply_two<1, 0, LAM>(s, a, sg, base, dre, dim); break;
+            case 5: apply_two<1, 2, LAM>(s, a, sg, base, dre, dim); break;
+            case 6: apply_two<2, 0, LAM>(s, a, sg, base, dre, dim); break;
+            default: apply_two<2, 1, LAM>(s, a, sg, base, dre, dim); break;
           }
           break;
         }
         case kThree:
-          apply_three(s, a, sg, base, dre, dim);
+          apply_three<LAM>(s, a, sg, base, dre, dim);
           break;
         default:
-          apply_diag(s, a, sg, base, dre, dim);
+          apply_diag<LAM>(s, a, sg, base, dre, dim);
           break;
       }
     }
-    if (sg.dot >= 0) {
+    if (LAM && sg.dot >= 0) {
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) {
         dre += __shfl_xor(dre, o, 64);
@@ -237,9 +250,10 @@ __global__ __launch_bounds__(kSegBlock) void segment_adjoint_kernel(SegArgs a, t
 #pragma unroll
     for (int r = 0; r < 8; r++) {
       psi[base + a.off[r]] = V{R(s.pr[r]), R(s.pi[r])};
-      lam[base + a.off[r]] = V{R(s.lr[r]), R(s.li[r])};
+      if (LAM) lam[base + a.off[r]] = V{R(s.lr[r]), R(s.li[r])};
     }
   }
+  if (!LAM) return;
   __syncthreads();
   for (int j = threadIdx.x; j < a.ndots; j += kSegBlock) {
     double2 t = acc[j][0];
@@ -310,18 +324,21 @@ int local_bit(const std::vector<int>& S, int q) {
 }  // namespace
 
 diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<LocalGate>& gens,
-                            const std::vector<int>& diff, int n, SegmentPlan* out) {
+                            const std::vector<int>& diff, int n, SegmentPlan* out, bool forward) {
   if (n < 3) return fail(DIAQ_ERR_UNSUPPORTED, "segment sweep needs n >= 3");
   SegmentPlan& P = *out;
   P = SegmentPlan();
+  P.forward = forward;
   const int64_t G = int64_t(lg.size());
-  int64_t g = G - 1;
-  while (g >= 0) {
-    // grow the segment backwards from gate g
+  // the sweep visits gates from `g` towards `end` in steps of `dir`
+  const int64_t dir = forward ? 1 : -1, end = forward ? G : -1;
+  int64_t g = forward ? 0 : G - 1;
+  while (g != end) {
+    // grow the segment from gate g
     std::vector<int> S;
     std::vector<int64_t> members;
     int ndots = 0;
-    for (; g >= 0; g--) {
+    for (; g != end; g += dir) {
       const LocalGate& L = lg[size_t(g)];
       std::vector<int> T;
       if (!is_diag(L))
@@ -329,10 +346,11 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
       std::vector<int> U = S;
       for (int q : T)
         if (std::find(U.begin(), U.end(), q) == U.end()) U.push_back(q);
-      if (U.size() > 3 || int(members.size()) >= kSegMaxGates || (diff[size_t(g)] && ndots >= kSegMaxDots)) break;
+      const bool want_dot = !forward && diff[size_t(g)];
+      if (U.size() > 3 || int(members.size()) >= kSegMaxGates || (want_dot && ndots >= kSegMaxDots)) break;
       S = U;
       members.push_back(g);
-      if (diff[size_t(g)]) ndots++;
+      if (want_dot) ndots++;
     }
     pad_set(S, n);
     Segment seg;
@@ -345,8 +363,9 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
       SegGate sg;
       std::memset(&sg, 0, sizeof(sg));
       sg.cmask = L.cmask;
-      sg.dot = diff[size_t(m)] ? seg.ndots++ : -1;
+      sg.dot = (!forward && diff[size_t(m)]) ? seg.ndots++ : -1;
       if (sg.dot >= 0) P.dot_gate.push_back(m);
+      P.gate_of.push_back(m);
       sg.moff = int64_t(P.pool.size());
       const int d = 1 << L.k;
       auto push = [&](double re, double im) {
@@ -357,7 +376,7 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
         sg.kind = kDiag;
         sg.dk = L.k;
         for (int j = 0; j < L.k; j++) sg.q[j] = L.targets[j];
-        for (int r = 0; r < d; r++) push(L.m[r][r][0], -L.m[r][r][1]);  // U^dagger
+        for (int r = 0; r < d; r++) push(L.m[r][r][0], forward ? L.m[r][r][1] : -L.m[r][r][1]);
         if (sg.dot >= 0)
           for (int r = 0; r < d; r++) push(gens[size_t(m)].m[r][r][0], gens[size_t(m)].m[r][r][1]);
       } else {
@@ -385,7 +404,8 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
         for (int r = 0; r < d; r++)
           for (int c = 0; c < d; c++) {
             const int pr = perm[r], pc = perm[c];
-            push(L.m[pc][pr][0], -L.m[pc][pr][1]);  // U^dagger[r][c] = conj(U[c][r])
+            if (forward) push(L.m[pr][pc][0], L.m[pr][pc][1]);
+            else push(L.m[pc][pr][0], -L.m[pc][pr][1]);  // U^dagger[r][c] = conj(U[c][r])
           }
         if (sg.dot >= 0)
           for (int r = 0; r < d; r++)
@@ -426,12 +446,20 @@ diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan&
     a.ndots = seg.ndots;
     a.gates = dg + seg.first;
     a.pool = dp;
-    if (dt == DIAQ_C128)
-      hipLaunchKernelGGL(segment_adjoint_kernel<double>, dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+    if (P.forward) {
+      if (dt == DIAQ_C128)
+        hipLaunchKernelGGL((segment_kernel<double, false>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+                           static_cast<double2*>(psi), nullptr, nullptr);
+      else
+        hipLaunchKernelGGL((segment_kernel<float, false>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+                           static_cast<float2*>(psi), nullptr, nullptr);
+    } else if (dt == DIAQ_C128) {
+      hipLaunchKernelGGL((segment_kernel<double, true>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
                          static_cast<double2*>(psi), static_cast<double2*>(lam), partial);
-    else
-      hipLaunchKernelGGL(segment_adjoint_kernel<float>, dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+    } else {
+      hipLaunchKernelGGL((segment_kernel<float, true>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
                          static_cast<float2*>(psi), static_cast<float2*>(lam), partial);
+    }
     DIAQ_HIP(hipGetLastError());
     if (seg.ndots) {
       hipLaunchKernelGGL(segment_reduce_kernel, dim3(unsigned(seg.ndots)), dim3(256), 0, stream, partial, blocks,
@@ -455,6 +483,10 @@ void segment_table_host(const SegmentPlan& P, std::vector<char>& host, const std
   if (!P.gates.empty()) std::memcpy(host.data(), P.gates.data(), P.gates.size() * sizeof(SegGate));
   if (!P.pool.empty()) std::memcpy(host.data() + gb, P.pool.data(), P.pool.size() * sizeof(double));
   if (!slots.empty()) std::memcpy(host.data() + gb + pb, slots.data(), slots.size() * sizeof(int64_t));
+}
+
+size_t segment_pool_offset(const SegmentPlan& P) {
+  return ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
 }
 
 int64_t segment_blocks(int n) {
