@@ -318,29 +318,60 @@ __global__ void batch_reset_kernel(int32_t* queue, double* expvals, int64_t nc, 
   if (i < ng) grads[i] = 0.0;
 }
 // ---------------------------------------------------------------------------
-// Wide circuits: every gate is a grid-wide Alg. 3 launch (in place), issued
-// on side streams so several circuits are in flight at once.
+// Wide circuits (too large for one workgroup): all of them advance together.
+// Each step is one launch whose grid is the concatenation of every wide
+// circuit's workgroups (segment passes of the segmented Alg. 3 sweep, the
+// observable, the initial state), so a few dozen launches cover the lot and
+// the GPU is full even when each state alone would occupy a few CUs.
 // ---------------------------------------------------------------------------
 
 constexpr int kWideMinQubits = 15;
-constexpr int kWideStreams = 4;
+constexpr int kSideStreams = 1;  // the persistent kernel runs beside the wide steps
 constexpr int kObsBlock = 256;
 
-__global__ void wide_init_kernel(double2* psi, int64_t N) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride)
-    psi[i] = double2{i == 0 ? 1.0 : 0.0, 0.0};
+// One wide circuit's vectors for the grouped init / observable kernels.
+struct WideVec {
+  double2* psi;
+  double2* lam;
+  int64_t N;
+  const uint64_t* zm;
+  const double* coef;
+  int32_t nt;
+  int32_t pad;
+  double2* partial;
+  double2* eval;
+  int64_t block0;  // first workgroup of this circuit in the grouped grid (N / kObsBlock each)
+};
+
+__device__ __forceinline__ int find_item(const WideVec* __restrict__ list, int count) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (list[mid].block0 <= int64_t(blockIdx.x)) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kObsBlock) void grouped_init_kernel(const WideVec* __restrict__ list, int count) {
+  const WideVec& w = list[find_item(list, count)];
+  const int64_t i = (int64_t(blockIdx.x) - w.block0) * kObsBlock + threadIdx.x;
+  if (i < w.N) w.psi[i] = double2{i == 0 ? 1.0 : 0.0, 0.0};
 }
 
 // lambda = H psi for the diagonal observable; one partial <psi|lambda> per
 // workgroup.
-__global__ __launch_bounds__(kObsBlock) void wide_observable_kernel(const double2* __restrict__ psi,
-                                                                    double2* __restrict__ lam, int64_t N,
-                                                                    const uint64_t* __restrict__ zm,
-                                                                    const double* __restrict__ coef, int nt,
-                                                                    double2* __restrict__ partial) {
+__global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const WideVec* __restrict__ list, int count) {
+  const WideVec& w = list[find_item(list, count)];
+  const int64_t blk = int64_t(blockIdx.x) - w.block0;
+  const double2* __restrict__ psi = w.psi;
+  double2* __restrict__ lam = w.lam;
+  const uint64_t* __restrict__ zm = w.zm;
+  const double* __restrict__ coef = w.coef;
+  const int64_t N = w.N;
+  const int nt = w.nt;
   double re = 0, im = 0;
-  const int64_t i = int64_t(blockIdx.x) * kObsBlock + threadIdx.x;
+  const int64_t i = blk * kObsBlock + threadIdx.x;
   if (i < N) {
     double h = 0;
     for (int t = 0; t < nt; t++) h += (__popcll(uint64_t(i) & zm[t]) & 1) ? -coef[t] : coef[t];
@@ -359,11 +390,38 @@ __global__ __launch_bounds__(kObsBlock) void wide_observable_kernel(const double
   __syncthreads();
   if (threadIdx.x == 0) {
     double2 t = wsum[0];
-    for (int w = 1; w < kObsBlock / 64; w++) {
-      t.x += wsum[w].x;
-      t.y += wsum[w].y;
+    for (int q = 1; q < kObsBlock / 64; q++) {
+      t.x += wsum[q].x;
+      t.y += wsum[q].y;
     }
-    partial[blockIdx.x] = t;
+    w.partial[blk] = t;
+  }
+}
+
+// E of every wide circuit: workgroup c sums circuit c's observable partials
+// in a fixed order.
+__global__ __launch_bounds__(256) void grouped_eval_kernel(const WideVec* __restrict__ list) {
+  const WideVec& w = list[blockIdx.x];
+  const int64_t nb = (w.N + kObsBlock - 1) / kObsBlock;
+  double re = 0, im = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += 256) {
+    re += w.partial[b].x;
+    im += w.partial[b].y;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  __shared__ double2 ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = double2{re, im};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 t = ws[0];
+    for (int q = 1; q < 4; q++) {
+      t.x += ws[q].x;
+      t.y += ws[q].y;
+    }
+    *w.eval = t;
   }
 }
 
@@ -406,7 +464,7 @@ int rot_of(int kind) {
 }
 
 struct WideCirc {
-  int32_t c = 0, n = 0, slot = 0;
+  int32_t c = 0, n = 0;
   int64_t g0 = 0;    // first gate in the batch gate table
   int64_t s0 = 0;    // workspace offset of psi (lambda follows)
   int64_t t0 = 0;    // first observable term
@@ -418,6 +476,8 @@ struct WideCirc {
   std::vector<double> scale;
   SegmentPlan fwd, rev;        // forward pass and reverse sweep, several gates per pass
   size_t o_fwd = 0, o_rev = 0; // their device tables, offsets into the batch block
+  size_t o_part = 0;           // this circuit's partial sums (offset into the partial region)
+  int64_t npart = 0;           // entries
   void* d_fwd = nullptr;
   void* d_rev = nullptr;
 };
@@ -427,7 +487,7 @@ struct WideCirc {
 struct SegPatch {
   double* dst;
   int32_t rot;
-  int32_t diag;    // 1: the table holds the diagonal only
+  int32_t diag;    // 1: the table holds the diagonal only; 2: the diagonal's phase angles
   int32_t dim;     // 2 or 4
   int32_t dagger;  // 1: store U^dagger (reverse sweep)
   int64_t slot;    // theta index
@@ -443,7 +503,9 @@ __global__ void seg_patch_kernel(const SegPatch* __restrict__ patches, int64_t c
   double m[4][4][2];
   rot_matrix(p.rot, theta ? p.scale * theta[p.slot] : p.angle0, m);
   const double sg = p.dagger ? -1.0 : 1.0;
-  if (p.diag) {
+  if (p.diag == 2) {
+    for (int r = 0; r < p.dim; r++) p.dst[r] = sg * atan2(m[r][r][1], m[r][r][0]);
+  } else if (p.diag) {
     for (int r = 0; r < p.dim; r++) {
       p.dst[2 * r] = m[r][r][0];
       p.dst[2 * r + 1] = sg * m[r][r][1];
@@ -464,9 +526,9 @@ __global__ void seg_patch_kernel(const SegPatch* __restrict__ patches, int64_t c
 struct diaq_batch {
   diaq_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
-  hipStream_t side[diaq::kWideStreams] = {};
+  hipStream_t side[diaq::kSideStreams] = {};
   hipEvent_t fork = nullptr;
-  hipEvent_t join[diaq::kWideStreams] = {};
+  hipEvent_t join[diaq::kSideStreams] = {};
   int32_t ncirc = 0;
   int32_t nnarrow = 0;
   int64_t nparams = 0;
@@ -479,7 +541,10 @@ struct diaq_batch {
   diaq::WideDot* d_wmeta = nullptr;
   double2* d_dots = nullptr;
   double2* d_evals = nullptr;
-  double2* d_partial[diaq::kWideStreams] = {};
+  void* gmem = nullptr;          // grouped-launch descriptors
+  diaq::GroupedSweep gfwd, grev;
+  diaq::WideVec* d_wvec = nullptr;
+  int64_t wblocks = 0;           // workgroups of the grouped init / observable grids
   diaq::SegPatch* d_patch = nullptr;
   int64_t npatch = 0;
   double* pinned = nullptr;      // theta in, expvals + grads out
@@ -494,25 +559,6 @@ struct diaq_batch {
 
 namespace diaq {
 namespace {
-
-diaq_status_t enqueue_wide(diaq_batch* b, const WideCirc& w, hipStream_t s) {
-  diaq_ctx* ctx = b->ctx;
-  const int64_t N = int64_t(1) << w.n;
-  double2* psi = b->ws + w.s0;
-  double2* lam = psi + N;
-  double2* part = b->d_partial[w.slot];
-  hipLaunchKernelGGL(wide_init_kernel, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, psi, N);
-  DIAQ_HIP(hipGetLastError());
-  DIAQ_TRY(run_segments(ctx, s, w.fwd, w.n, DIAQ_C128, psi, nullptr, w.d_fwd, nullptr, nullptr));
-  const int64_t ob = (N + kObsBlock - 1) / kObsBlock;
-  hipLaunchKernelGGL(wide_observable_kernel, dim3(unsigned(ob)), dim3(kObsBlock), 0, s, psi, lam, N,
-                     b->args.zmask + w.t0, b->args.coef + w.t0, w.nt, part);
-  DIAQ_HIP(hipGetLastError());
-  const int64_t wi = &w - b->wide.data();
-  DIAQ_TRY(launch_final_reduce(s, part, ob, reinterpret_cast<double*>(b->d_evals + wi)));
-  DIAQ_TRY(run_segments(ctx, s, w.rev, w.n, DIAQ_C128, psi, lam, w.d_rev, part, reinterpret_cast<double*>(b->d_dots)));
-  return DIAQ_OK;
-}
 
 diaq_status_t enqueue(diaq_batch* b, bool use_theta) {
   BatchArgs args = b->args;
@@ -535,24 +581,36 @@ diaq_status_t enqueue(diaq_batch* b, bool use_theta) {
                        b->npatch, use_theta ? args.theta : nullptr);
     DIAQ_HIP(hipGetLastError());
   }
-  if (wide) {
+  // the persistent kernel runs on the side stream while the wide circuits
+  // step together on the batch stream
+  const bool side = wide && b->nnarrow;
+  if (side) {
     DIAQ_HIP(hipEventRecord(b->fork, b->stream));
-    for (int j = 0; j < kWideStreams; j++) DIAQ_HIP(hipStreamWaitEvent(b->side[j], b->fork, 0));
+    DIAQ_HIP(hipStreamWaitEvent(b->side[0], b->fork, 0));
   }
   if (b->nnarrow) {
-    hipLaunchKernelGGL(batch_kernel, dim3(unsigned(b->grid)), dim3(kThreads), b->lds_bytes, b->stream, args);
+    hipLaunchKernelGGL(batch_kernel, dim3(unsigned(b->grid)), dim3(kThreads), b->lds_bytes,
+                       side ? b->side[0] : b->stream, args);
     DIAQ_HIP(hipGetLastError());
   }
   if (wide) {
-    for (const auto& w : b->wide) DIAQ_TRY(enqueue_wide(b, w, b->side[w.slot]));
-    for (int j = 0; j < kWideStreams; j++) {
-      DIAQ_HIP(hipEventRecord(b->join[j], b->side[j]));
-      DIAQ_HIP(hipStreamWaitEvent(b->stream, b->join[j], 0));
-    }
     const int nw = int(b->wide.size());
+    hipLaunchKernelGGL(grouped_init_kernel, dim3(unsigned(b->wblocks)), dim3(kObsBlock), 0, b->stream, b->d_wvec, nw);
+    DIAQ_HIP(hipGetLastError());
+    DIAQ_TRY(run_grouped(b->stream, b->gfwd, nullptr));
+    hipLaunchKernelGGL(grouped_observable_kernel, dim3(unsigned(b->wblocks)), dim3(kObsBlock), 0, b->stream,
+                       b->d_wvec, nw);
+    DIAQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(grouped_eval_kernel, dim3(unsigned(nw)), dim3(256), 0, b->stream, b->d_wvec);
+    DIAQ_HIP(hipGetLastError());
+    DIAQ_TRY(run_grouped(b->stream, b->grev, reinterpret_cast<double*>(b->d_dots)));
     hipLaunchKernelGGL(wide_finalize_kernel, dim3(unsigned((nw + 63) / 64)), dim3(64), 0, b->stream, b->d_wres, nw,
                        b->d_wmeta, b->d_dots, b->d_evals, args.expvals, args.grads);
     DIAQ_HIP(hipGetLastError());
+  }
+  if (side) {
+    DIAQ_HIP(hipEventRecord(b->join[0], b->side[0]));
+    DIAQ_HIP(hipStreamWaitEvent(b->stream, b->join[0], 0));
   }
   double* out = b->pinned + b->pinned_theta;
   DIAQ_HIP(hipMemcpyAsync(out, args.expvals, size_t(b->ncirc) * sizeof(double), hipMemcpyDeviceToHost, b->stream));
@@ -572,15 +630,16 @@ extern "C" {
 diaq_status_t diaq_batch_free(diaq_batch_t b) {
   if (!b) return DIAQ_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  for (int j = 0; j < kWideStreams; j++)
+  for (int j = 0; j < kSideStreams; j++)
     if (b->side[j]) (void)hipStreamSynchronize(b->side[j]);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->g) (void)hipGraphDestroy(b->g);
   if (b->dmem) (void)hipFree(b->dmem);
+  if (b->gmem) (void)hipFree(b->gmem);
   if (b->ws) (void)hipFree(b->ws);
   if (b->pinned) (void)hipHostFree(b->pinned);
   if (b->fork) (void)hipEventDestroy(b->fork);
-  for (int j = 0; j < kWideStreams; j++) {
+  for (int j = 0; j < kSideStreams; j++) {
     if (b->join[j]) (void)hipEventDestroy(b->join[j]);
     if (b->side[j]) (void)hipStreamDestroy(b->side[j]);
   }
@@ -695,9 +754,20 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
         r.dot0 = int64_t(wmeta.size());
         r.p0 = bc.p0;
         wc.dot0 = r.dot0;
-        // dot slots in reverse-sweep order
-        for (int64_t gi = C.ngates - 1; gi >= 0; gi--)
-          if (wc.pidx[size_t(gi)] >= 0) wmeta.push_back(WideDot{wc.pidx[size_t(gi)], 0, C.gates[gi].param_scale});
+        // segment plans; dot slots in the reverse sweep's order (gates that
+        // share a parameter and scale inside a diagonal run share a dot)
+        std::vector<int64_t> dkey(wc.lg.size(), -1);
+        for (size_t j = 0; j < wc.lg.size(); j++)
+          if (wc.pidx[j] >= 0) {
+            int64_t key = -1;
+            for (size_t i2 = 0; i2 < j && key < 0; i2++)
+              if (wc.pidx[i2] == wc.pidx[j] && wc.scale[i2] == wc.scale[j]) key = dkey[i2];
+            dkey[j] = key >= 0 ? key : int64_t(j);
+          }
+        DIAQ_TRY(plan_segments(wc.lg, wc.gen, dkey, wc.n, &wc.fwd, true));
+        DIAQ_TRY(plan_segments(wc.lg, wc.gen, dkey, wc.n, &wc.rev, false));
+        for (int64_t gi : wc.rev.dot_gate)
+          wmeta.push_back(WideDot{wc.pidx[size_t(gi)], 0, wc.scale[size_t(gi)]});
         r.ndots = int32_t(int64_t(wmeta.size()) - r.dot0);
         wres.push_back(r);
         wide.push_back(std::move(wc));
@@ -705,32 +775,18 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
         narrow.push_back(c);
       }
     }
-    // narrow circuits: queue order, largest work first; wide circuits:
-    // greedy assignment of the largest to the least-loaded side stream
+    // narrow circuits: queue order, largest work first
     std::stable_sort(narrow.begin(), narrow.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
-    {
-      std::vector<size_t> idx(wide.size());
-      std::iota(idx.begin(), idx.end(), 0);
-      std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return work[wide[x].c] > work[wide[y].c]; });
-      double load[kWideStreams] = {0, 0, 0, 0};
-      for (size_t x : idx) {
-        int best = 0;
-        for (int j = 1; j < kWideStreams; j++)
-          if (load[j] < load[best]) best = j;
-        wide[x].slot = best;
-        load[best] += work[wide[x].c];
-      }
-    }
-    int64_t maxpart = 1;
+    size_t part_bytes = 0;
     size_t seg_bytes = 0;
     std::vector<std::vector<char>> seg_host;
     for (auto& w : wide) {
-      maxpart = std::max<int64_t>(maxpart, ((int64_t(1) << w.n) + kObsBlock - 1) / kObsBlock);
-      maxpart = std::max<int64_t>(maxpart, segment_blocks(w.n) * kSegMaxDots);
-      std::vector<int> diff(w.lg.size());
-      for (size_t j = 0; j < w.lg.size(); j++) diff[j] = w.pidx[j] >= 0 ? 1 : 0;
-      DIAQ_TRY(plan_segments(w.lg, w.gen, diff, w.n, &w.fwd, true));
-      DIAQ_TRY(plan_segments(w.lg, w.gen, diff, w.n, &w.rev, false));
+      // partial sums: the observable's, and the reverse sweep's per-segment dots
+      int32_t maxdots = 1;
+      for (const auto& sg : w.rev.segs) maxdots = std::max(maxdots, sg.ndots);
+      w.npart = std::max<int64_t>(((int64_t(1) << w.n) + kObsBlock - 1) / kObsBlock, segment_blocks(w.n) * maxdots);
+      w.o_part = part_bytes;
+      part_bytes += (size_t(w.npart) * sizeof(double2) + 255) / 256 * 256;
       std::vector<int64_t> slots(w.rev.dot_gate.size());
       for (size_t j = 0; j < slots.size(); j++) slots[j] = w.dot0 + int64_t(j);
       seg_host.emplace_back();
@@ -752,11 +808,16 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
       diaq_batch_free(b);
       return st;
     };
+#define DIAQ_TRY_BAIL(expr)              \
+  do {                                   \
+    diaq_status_t s_ = (expr);           \
+    if (s_ != DIAQ_OK) return bail(s_);  \
+  } while (0)
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
       return bail(fail(DIAQ_ERR_DEVICE, "hipStreamCreate failed"));
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
       return bail(fail(DIAQ_ERR_DEVICE, "hipEventCreate failed"));
-    for (int j = 0; j < kWideStreams; j++) {
+    for (int j = 0; j < kSideStreams; j++) {
       if (hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&b->join[j], hipEventDisableTiming) != hipSuccess)
         return bail(fail(DIAQ_ERR_DEVICE, "side stream setup failed"));
@@ -778,7 +839,7 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     const size_t o_wmeta = off; off += al(wmeta.size() * sizeof(WideDot) + 1);
     const size_t o_dots = off; off += al(wmeta.size() * sizeof(double2) + 1);
     const size_t o_evals = off; off += al(wide.size() * sizeof(double2) + 1);
-    const size_t o_part = off; off += al(size_t(maxpart) * sizeof(double2)) * kWideStreams;
+    const size_t o_part = off; off += al(part_bytes + 1);
     const size_t o_seg = off; off += al(seg_bytes + 1);
     // matrices of rotations inside the segment tables
     std::vector<SegPatch> patches;
@@ -790,7 +851,8 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
           SegPatch sp;
           std::memset(&sp, 0, sizeof(sp));
           sp.rot = w.rot[size_t(m)];
-          sp.diag = P->gates[i].kind == 3 ? 1 : 0;
+          if (P->gates[i].kind == 4) continue;  // run header
+          sp.diag = P->gates[i].kind == 5 ? 2 : P->gates[i].kind == 3 ? 1 : 0;
           sp.dim = sp.diag ? (1 << P->gates[i].dk) : (P->gates[i].kind == 0 ? 2 : 4);
           sp.dagger = P->forward ? 0 : 1;
           sp.slot = circ[size_t(w.c)].p0 + w.pidx[size_t(m)];
@@ -849,8 +911,49 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
     b->d_evals = reinterpret_cast<double2*>(base + o_evals);
     b->d_patch = reinterpret_cast<SegPatch*>(base + o_patch);
     b->npatch = int64_t(patches.size());
-    for (int j = 0; j < kWideStreams; j++)
-      b->d_partial[j] = reinterpret_cast<double2*>(base + o_part + size_t(j) * al(size_t(maxpart) * sizeof(double2)));
+    // grouped-launch descriptors (they hold the device addresses set above)
+    if (!wide.empty()) {
+      std::vector<GroupItem> fi, ri;
+      std::vector<WideVec> wv;
+      int64_t blocks = 0;
+      for (size_t x = 0; x < wide.size(); x++) {
+        const WideCirc& w = wide[x];
+        const int64_t N = int64_t(1) << w.n;
+        double2* psi = b->ws + w.s0;
+        double2* part = reinterpret_cast<double2*>(base + o_part + w.o_part);
+        fi.push_back(GroupItem{&w.fwd, w.d_fwd, w.n, psi, nullptr, nullptr});
+        ri.push_back(GroupItem{&w.rev, w.d_rev, w.n, psi, psi + N, part});
+        WideVec v;
+        std::memset(&v, 0, sizeof(v));
+        v.psi = psi;
+        v.lam = psi + N;
+        v.N = N;
+        v.zm = b->args.zmask + w.t0;
+        v.coef = b->args.coef + w.t0;
+        v.nt = w.nt;
+        v.partial = part;
+        v.eval = b->d_evals + x;
+        v.block0 = blocks;
+        blocks += (N + kObsBlock - 1) / kObsBlock;
+        wv.push_back(v);
+      }
+      DIAQ_TRY_BAIL(build_grouped(fi, true, &b->gfwd));
+      DIAQ_TRY_BAIL(build_grouped(ri, false, &b->grev));
+      const size_t gf = al(b->gfwd.host.size()), gr = al(b->grev.host.size()), gv = al(wv.size() * sizeof(WideVec));
+      if (hipMalloc(&b->gmem, gf + gr + gv) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(DIAQ_ERR_OUT_OF_MEMORY, "batch launch tables: %zu bytes", gf + gr + gv));
+      }
+      char* gb = static_cast<char*>(b->gmem);
+      e = hipMemcpy(gb, b->gfwd.host.data(), b->gfwd.host.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(gb + gf, b->grev.host.data(), b->grev.host.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(gb + gf + gr, wv.data(), wv.size() * sizeof(WideVec), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return bail(fail(DIAQ_ERR_DEVICE, "batch upload: %s", hipGetErrorString(e)));
+      b->gfwd.dev = gb;
+      b->grev.dev = gb + gf;
+      b->d_wvec = reinterpret_cast<WideVec*>(gb + gf + gr);
+      b->wblocks = blocks;
+    }
     b->ngates = int64_t(gates.size());
     b->wide = std::move(wide);
     b->pinned_theta = nparams;

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <map>
+
 #include "internal.hpp"
 
 namespace diaq {
@@ -328,7 +330,20 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     SegmentPlan sp;
     std::vector<char> table;
     if (segmented) {
-      DIAQ_TRY(plan_segments(p.lg, gens, diff, nqubits, &sp));
+      // dot keys: gates with the same parameter and scale may share a dot
+      std::vector<int64_t> dkey(size_t(ngates), -1);
+      std::map<std::pair<int32_t, double>, int64_t> keys;
+      for (int64_t g = 0; g < ngates; g++)
+        if (diff[size_t(g)]) {
+          const auto k = std::make_pair(gates[g].param_index, gates[g].param_scale);
+          auto it = keys.find(k);
+          if (it == keys.end()) {
+            const int64_t id = int64_t(keys.size());
+            it = keys.emplace(k, id).first;
+          }
+          dkey[size_t(g)] = it->second;
+        }
+      DIAQ_TRY(plan_segments(p.lg, gens, dkey, nqubits, &sp));
       std::vector<int64_t> slots(sp.dot_gate.size());
       for (size_t j = 0; j < slots.size(); j++) slots[j] = sp.dot_gate[j] + 1;
       segment_table_host(sp, table, slots);

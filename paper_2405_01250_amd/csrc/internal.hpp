@@ -231,7 +231,8 @@ double kron_op_bytes(const LocalGate& core, int nf, int n, diaq_dtype_t dt);
 // One gate of a segment in the coset's local basis (bit j of a local index
 // is qubit S[j], S ascending).
 struct SegGate {
-  int32_t kind;     // 0: one target, 1: two targets, 2: three targets (= S), 3: diagonal
+  int32_t kind;     // 0: one target, 1: two targets, 2: three targets (= S), 3: diagonal,
+                    // 4: header of a run of b0 diagonal phase gates, 5: member of a run
   int32_t b0, b1;   // local bits of targets 0 and 1 (kinds 0, 1)
   int32_t dot;      // slot of this gate's dot within the segment, -1 if none
   int32_t dk;       // diagonal: number of qubits in q
@@ -246,6 +247,8 @@ struct Segment {
   int64_t ngates = 0;
   int32_t ndots = 0;
   int64_t dot_slot0 = 0;  // first entry of SegmentPlan::dot_gate
+  bool three = false;     // holds a three-target gate
+  int64_t pool_lo = 0, pool_n = 0;  // its matrices in SegmentPlan::pool
 };
 
 struct SegmentPlan {
@@ -258,14 +261,17 @@ struct SegmentPlan {
 };
 
 constexpr int kSegMaxDots = 64;
-constexpr int kSegMaxGates = 512;
+constexpr int kSegLdsGates = 128;   // SegGate entries of one segment (staged in LDS)
+constexpr int kSegLdsPool = 2048;   // matrix doubles of one segment (staged in LDS)
 
 // Cut the reverse sweep (or, with forward, the circuit in its own order)
 // into segments: consecutive gates whose non-diagonal targets fit in 3
-// qubits (diagonal gates and controls anywhere).  diff[g] marks gates whose
-// dot the reverse sweep takes; gens[g] is then their generator.
+// qubits (diagonal gates and controls anywhere).  dkey[g] >= 0 marks gates
+// whose dot the reverse sweep takes (gens[g] is then their generator);
+// consecutive diagonal gates with equal keys (same parameter and scale)
+// share one dot, stored at the first of them (SegmentPlan::dot_gate).
 diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<LocalGate>& gens,
-                            const std::vector<int>& diff, int n, SegmentPlan* out, bool forward = false);
+                            const std::vector<int64_t>& dkey, int n, SegmentPlan* out, bool forward = false);
 // Device table layout [gates | pool | dot output slots]: its size, and its
 // host image with slots[j] = output slot (pairs of doubles) of dot j.
 size_t segment_table_bytes(const SegmentPlan& P);
@@ -273,6 +279,34 @@ void segment_table_host(const SegmentPlan& P, std::vector<char>& host, const std
 int64_t segment_blocks(int n);
 // Byte offset of the matrix pool inside the device table.
 size_t segment_pool_offset(const SegmentPlan& P);
+
+// Grouped sweeps over many independent complex128 states: step k runs
+// segment k of every item's plan in one launch (workgroups of the items one
+// after another), then, for reverse plans, all of that step's dot sums in a
+// second launch.  The descriptors hold device pointers only; `host` is
+// their image, to be copied to `dev` (G.host.size() bytes) before running.
+struct GroupItem {
+  const SegmentPlan* plan;
+  const void* table;     // device table of the plan
+  int n;
+  void* psi;
+  void* lam;             // reverse plans
+  double2* partial;      // reverse plans: segment_blocks(n) * (max dots of a segment) entries
+};
+struct GroupedStep {
+  int64_t seg_first = 0, seg_count = 0, blocks = 0;
+  int64_t red_first = 0, red_count = 0, red_blocks = 0;
+  bool three = false;
+};
+struct GroupedSweep {
+  bool forward = false;
+  std::vector<GroupedStep> steps;
+  std::vector<char> host;
+  size_t red_offset = 0;
+  const void* dev = nullptr;
+};
+diaq_status_t build_grouped(const std::vector<GroupItem>& items, bool forward, GroupedSweep* out);
+diaq_status_t run_grouped(hipStream_t stream, const GroupedSweep& G, double* dots);
 // Run the sweep: for every segment one pass over psi and lambda (each dot
 // taken before its gate is undone), then the fixed-order dot sums into
 // dots[2 * slot], dots[2 * slot + 1].  partial holds segment_blocks(n) *

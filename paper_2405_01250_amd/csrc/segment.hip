@@ -22,6 +22,7 @@
 // per-gate matrices (refreshed on the device from new angles) serves both
 // passes.
 #include <algorithm>
+#include <cmath>
 
 #include "internal.hpp"
 
@@ -31,8 +32,9 @@ namespace {
 
 constexpr int kSegBlock = 256;
 constexpr int kSegWaves = kSegBlock / 64;
+static_assert(sizeof(SegGate) % sizeof(uint64_t) == 0, "SegGate is copied in 8-byte words");
 
-enum SegKind : int32_t { kOne = 0, kTwo = 1, kThree = 2, kDiag = 3 };
+enum SegKind : int32_t { kOne = 0, kTwo = 1, kThree = 2, kDiag = 3, kRun = 4, kRunMember = 5 };
 
 struct SegArgs {
   int64_t ncos;        // N / 8
@@ -43,6 +45,8 @@ struct SegArgs {
   int64_t off[8];      // global offset of local index r
   const SegGate* gates;
   const double* pool;
+  int64_t pool_lo;     // the segment's matrices: pool[pool_lo, pool_lo + pool_n)
+  int64_t pool_n;
 };
 
 template <typename R>
@@ -54,6 +58,27 @@ struct Vec<double> {
 template <>
 struct Vec<float> {
   using V = float2;
+};
+
+// Pointers that arrive through memory (the grouped launches' descriptors)
+// are generic; casting them to the global address space keeps their
+// accesses off the flat path, whose waits would also stall on LDS reads.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+
+// Native two-element vectors (the element type of interleaved complex
+// arrays) for loads and stores through global-space pointers.
+template <typename R>
+struct Nat;
+template <>
+struct Nat<double> {
+  typedef double T __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Nat<float> {
+  typedef float T __attribute__((ext_vector_type(2)));
 };
 
 struct Coset {
@@ -117,6 +142,8 @@ __device__ __forceinline__ void apply_one(Coset& s, const SegArgs& a, const SegG
   const double* g = sg.dot >= 0 ? m + 8 : nullptr;
 #pragma unroll
   for (int p = 0; p < 4; p++) {
+    // re-read the matrix from LDS for every pair rather than keep it in registers
+    __asm__ volatile("" ::: "memory");
     const int r0 = ((p >> B) << (B + 1)) | (p & ((1 << B) - 1));
     const int idx[2] = {r0, r0 | (1 << B)};
     if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
@@ -133,6 +160,7 @@ __device__ __forceinline__ void apply_two(Coset& s, const SegArgs& a, const SegG
   const double* g = sg.dot >= 0 ? m + 32 : nullptr;
 #pragma unroll
   for (int p = 0; p < 2; p++) {
+    __asm__ volatile("" ::: "memory");
     const int r0 = p ? FREE : 0;
     const int idx[4] = {r0, r0 | (1 << B0), r0 | (1 << B1), r0 | (1 << B0) | (1 << B1)};
     if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
@@ -150,6 +178,8 @@ __device__ __forceinline__ void apply_three(Coset& s, const SegArgs& a, const Se
   local_apply<8, LAM>(s, idx, m, g, dre, dim);
 }
 
+// Diagonal gate on any qubits: each amplitude reads its entry of the
+// gate's (at most 8-entry) table.
 template <bool LAM>
 __device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
                                            double& dim) {
@@ -160,7 +190,9 @@ __device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const Seg
     const uint64_t i = uint64_t(base + a.off[r]);
     if ((i & sg.cmask) != sg.cmask) continue;
     int t = 0;
-    for (int j = 0; j < sg.dk; j++) t |= int((i >> sg.q[j]) & 1) << j;
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+      if (j < sg.dk) t |= int((i >> sg.q[j]) & 1) << j;
     if (LAM && sg.dot >= 0) {
       const double gr = g[2 * t] * s.pr[r] - g[2 * t + 1] * s.pi[r];
       const double gi = g[2 * t] * s.pi[r] + g[2 * t + 1] * s.pr[r];
@@ -179,14 +211,104 @@ __device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const Seg
   }
 }
 
-template <typename R, bool LAM>
-__global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename Vec<R>::V* __restrict__ psi,
-                                                                    typename Vec<R>::V* __restrict__ lam,
-                                                                    double2* __restrict__ partial) {
-  using V = typename Vec<R>::V;
+// Wave sum of one dot, parked in LDS for the workgroup's partial.
+__device__ __forceinline__ void flush_dot(double2 (*acc)[kSegBlock / 64], int j, double dre, double dim) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    dre += __shfl_xor(dre, o, 64);
+    dim += __shfl_xor(dim, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) acc[j][threadIdx.x >> 6] = double2{dre, dim};
+}
+
+// A run of m diagonal gates (the m entries after the header).  They commute,
+// so every dot may be taken at the start of the run, where it is
+// sum_i G(i) conj(lambda_i) psi_i (the generators are real and diagonal);
+// the phases add up as angles and are applied once.  Consecutive members
+// that share a dot slot (same parameter and scale) add into one dot.
+template <bool LAM>
+__device__ __forceinline__ void apply_run(Coset& s, const SegArgs& a, int gi, int m, int64_t base,
+                                          double2 (*acc)[kSegBlock / 64]) {
+  double ang[8], wr[8], wi[8];
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    ang[r] = 0.0;
+    if (LAM) {
+      wr[r] = s.lr[r] * s.pr[r] + s.li[r] * s.pi[r];
+      wi[r] = s.lr[r] * s.pi[r] - s.li[r] * s.pr[r];
+    }
+  }
+  int cur = -1;
+  double dre = 0, dim = 0;
+  for (int k = 1; k <= m; k++) {
+    const SegGate mg = a.gates[gi + k];
+    if (LAM && mg.dot >= 0 && mg.dot != cur) {
+      if (cur >= 0) flush_dot(acc, cur, dre, dim);
+      cur = mg.dot;
+      dre = dim = 0;
+    }
+    const double* at = a.pool + mg.moff;
+    const double* gt = at + (1 << mg.dk);
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+      const uint64_t i = uint64_t(base + a.off[r]);
+      if ((i & mg.cmask) != mg.cmask) continue;
+      int t = 0;
+#pragma unroll
+      for (int j = 0; j < 3; j++)
+        if (j < mg.dk) t |= int((i >> mg.q[j]) & 1) << j;
+      ang[r] += at[t];
+      if (LAM && mg.dot >= 0) {
+        const double g = gt[t];
+        dre += g * wr[r];
+        dim += g * wi[r];
+      }
+    }
+  }
+  if (LAM && cur >= 0) flush_dot(acc, cur, dre, dim);
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    double sn, cs;
+    sincos(ang[r], &sn, &cs);
+    double x = cs * s.pr[r] - sn * s.pi[r];
+    s.pi[r] = cs * s.pi[r] + sn * s.pr[r];
+    s.pr[r] = x;
+    if (LAM) {
+      x = cs * s.lr[r] - sn * s.li[r];
+      s.li[r] = cs * s.li[r] + sn * s.lr[r];
+      s.lr[r] = x;
+    }
+  }
+}
+
+// One workgroup's share of a segment pass: workgroup `block` of the grid
+// over a's cosets.
+template <typename R, bool LAM, bool T3>
+__device__ __forceinline__ void segment_body(const SegArgs& ga, typename Vec<R>::V* psi_in,
+                                             typename Vec<R>::V* lam_in, double2* partial_in, int64_t block) {
+  using NV = typename Nat<R>::T;
+  using ND = typename Nat<double>::T;
+  auto* __restrict__ psi = gptr(reinterpret_cast<NV*>(psi_in));
+  auto* __restrict__ lam = gptr(reinterpret_cast<NV*>(lam_in));
+  auto* __restrict__ partial = gptr(reinterpret_cast<ND*>(partial_in));
   __shared__ double2 acc[kSegMaxDots][kSegWaves];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t c = int64_t(blockIdx.x) * kSegBlock + threadIdx.x;
+  // the segment's gate list and matrices, staged in LDS: every lane reads
+  // the same entries, gate after gate
+  __shared__ SegGate lgates[kSegLdsGates];
+  __shared__ double lpool[kSegLdsPool];
+  {
+    const int words = ga.ngates * int(sizeof(SegGate) / sizeof(uint64_t));
+    const auto* src = gptr(reinterpret_cast<const uint64_t*>(ga.gates));
+    uint64_t* dst = reinterpret_cast<uint64_t*>(lgates);
+    for (int t = threadIdx.x; t < words; t += kSegBlock) dst[t] = src[t];
+    const auto* pool = gptr(ga.pool);
+    for (int t = threadIdx.x; t < int(ga.pool_n); t += kSegBlock) lpool[t] = pool[ga.pool_lo + t];
+  }
+  SegArgs a = ga;
+  a.gates = lgates;
+  a.pool = lpool - ga.pool_lo;
+  __syncthreads();
+  const int64_t c = block * kSegBlock + threadIdx.x;
   const bool live = c < a.ncos;
   int64_t base = 0;
   if (live) {
@@ -200,8 +322,8 @@ __global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename 
   Coset s;
 #pragma unroll
   for (int r = 0; r < 8; r++) {
-    V x = live ? psi[base + a.off[r]] : V{0, 0};
-    V y = (LAM && live) ? lam[base + a.off[r]] : V{0, 0};
+    NV x = live ? psi[base + a.off[r]] : NV{R(0), R(0)};
+    NV y = (LAM && live) ? lam[base + a.off[r]] : NV{R(0), R(0)};
     s.pr[r] = double(x.x);
     s.pi[r] = double(x.y);
     s.lr[r] = double(y.x);
@@ -209,6 +331,11 @@ __global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename 
   }
   for (int gi = 0; gi < a.ngates; gi++) {
     const SegGate sg = a.gates[gi];
+    if (sg.kind == kRun) {
+      apply_run<LAM>(s, a, gi, sg.b0, base, acc);
+      gi += sg.b0;
+      continue;
+    }
     double dre = 0, dim = 0;
     if (live) {
       switch (sg.kind) {
@@ -230,27 +357,20 @@ __global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename 
           break;
         }
         case kThree:
-          apply_three<LAM>(s, a, sg, base, dre, dim);
+          if constexpr (T3) apply_three<LAM>(s, a, sg, base, dre, dim);
           break;
         default:
           apply_diag<LAM>(s, a, sg, base, dre, dim);
           break;
       }
     }
-    if (LAM && sg.dot >= 0) {
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        dre += __shfl_xor(dre, o, 64);
-        dim += __shfl_xor(dim, o, 64);
-      }
-      if (lane == 0) acc[sg.dot][wave] = double2{dre, dim};
-    }
+    if (LAM && sg.dot >= 0) flush_dot(acc, sg.dot, dre, dim);
   }
   if (live) {
 #pragma unroll
     for (int r = 0; r < 8; r++) {
-      psi[base + a.off[r]] = V{R(s.pr[r]), R(s.pi[r])};
-      if (LAM) lam[base + a.off[r]] = V{R(s.lr[r]), R(s.li[r])};
+      psi[base + a.off[r]] = NV{R(s.pr[r]), R(s.pi[r])};
+      if (LAM) lam[base + a.off[r]] = NV{R(s.lr[r]), R(s.li[r])};
     }
   }
   if (!LAM) return;
@@ -261,8 +381,38 @@ __global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename 
       t.x += acc[j][w].x;
       t.y += acc[j][w].y;
     }
-    partial[int64_t(blockIdx.x) * a.ndots + j] = t;
+    partial[block * a.ndots + j] = ND{t.x, t.y};
   }
+}
+
+template <typename R, bool LAM, bool T3>
+__global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename Vec<R>::V* __restrict__ psi,
+                                                            typename Vec<R>::V* __restrict__ lam,
+                                                            double2* __restrict__ partial) {
+  segment_body<R, LAM, T3>(a, psi, lam, partial, blockIdx.x);
+}
+
+// Grouped launch: segment passes over many independent states in one grid;
+// each state's workgroups follow the previous state's.
+struct GroupSeg {
+  SegArgs a;
+  void* psi;
+  void* lam;
+  double2* partial;
+  int64_t block0;
+};
+
+template <typename R, bool LAM, bool T3>
+__global__ __launch_bounds__(kSegBlock) void grouped_segment_kernel(const GroupSeg* __restrict__ list, int count) {
+  int lo = 0, hi = count - 1;  // last item with block0 <= blockIdx.x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (list[mid].block0 <= int64_t(blockIdx.x)) lo = mid;
+    else hi = mid - 1;
+  }
+  const GroupSeg& g = list[lo];
+  segment_body<R, LAM, T3>(g.a, static_cast<typename Vec<R>::V*>(g.psi), static_cast<typename Vec<R>::V*>(g.lam),
+                           g.partial, int64_t(blockIdx.x) - g.block0);
 }
 
 // Dot j of a segment: the partials of all workgroups summed in a fixed
@@ -295,6 +445,85 @@ __global__ __launch_bounds__(256) void segment_reduce_kernel(const double2* __re
   }
 }
 
+template <typename R, bool T3>
+void launch_segment(bool forward, int64_t blocks, hipStream_t stream, const SegArgs& a, void* psi, void* lam,
+                    double2* partial) {
+  using V = typename Vec<R>::V;
+  if (forward)
+    hipLaunchKernelGGL((segment_kernel<R, false, T3>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+                       static_cast<V*>(psi), nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((segment_kernel<R, true, T3>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
+                       static_cast<V*>(psi), static_cast<V*>(lam), partial);
+}
+
+// Grouped dot sums: workgroup b handles dot (b - red0) of its item.
+struct GroupRed {
+  const double2* partial;
+  int64_t blocks;
+  int32_t ndots;
+  int32_t pad;
+  const int64_t* slot;
+  int64_t red0;
+};
+
+__global__ __launch_bounds__(256) void grouped_reduce_kernel(const GroupRed* __restrict__ list, int count,
+                                                             double* __restrict__ out) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (list[mid].red0 <= int64_t(blockIdx.x)) lo = mid;
+    else hi = mid - 1;
+  }
+  const GroupRed& g = list[lo];
+  const int j = int(int64_t(blockIdx.x) - g.red0);
+  const auto* part = gptr(reinterpret_cast<const typename Nat<double>::T*>(g.partial));
+  double re = 0, im = 0;
+  for (int64_t b = threadIdx.x; b < g.blocks; b += 256) {
+    const auto v = part[b * g.ndots + j];
+    re += v.x;
+    im += v.y;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  __shared__ double2 ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = double2{re, im};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 t = ws[0];
+    for (int w = 1; w < 4; w++) {
+      t.x += ws[w].x;
+      t.y += ws[w].y;
+    }
+    const int64_t sl = gptr(g.slot)[j];
+    out[2 * sl] = t.x;
+    out[2 * sl + 1] = t.y;
+  }
+}
+
+SegArgs make_seg_args(const Segment& seg, int n, const SegGate* dg, const double* dp) {
+  SegArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ncos = (int64_t(1) << n) >> 3;
+  for (int j = 0; j < 3; j++) a.sorted[j] = seg.S[j];
+  for (int r = 0; r < 8; r++) {
+    int64_t o = 0;
+    for (int j = 0; j < 3; j++)
+      if ((r >> j) & 1) o |= int64_t(1) << seg.S[j];
+    a.off[r] = o;
+  }
+  a.ngates = int32_t(seg.ngates);
+  a.ndots = seg.ndots;
+  a.gates = dg + seg.first;
+  a.pool = dp;
+  a.pool_lo = seg.pool_lo;
+  a.pool_n = seg.pool_n;
+  return a;
+}
+
 bool is_diag(const LocalGate& lg) {
   const int d = 1 << lg.k;
   for (int r = 0; r < d; r++)
@@ -317,6 +546,17 @@ void pad_set(std::vector<int>& S, int n) {
   std::sort(S.begin(), S.end());
 }
 
+// A diagonal gate that can join a run: its entries are pure phases (stored
+// as angles) and, when its dot is wanted, its generator is real.
+bool run_member(const LocalGate& L, const LocalGate& gen, bool dot) {
+  if (!is_diag(L)) return false;
+  for (int r = 0; r < (1 << L.k); r++) {
+    if (std::fabs(std::hypot(L.m[r][r][0], L.m[r][r][1]) - 1.0) > 1e-13) return false;
+    if (dot && gen.m[r][r][1] != 0.0) return false;
+  }
+  return true;
+}
+
 int local_bit(const std::vector<int>& S, int q) {
   return int(std::find(S.begin(), S.end(), q) - S.begin());
 }
@@ -324,7 +564,7 @@ int local_bit(const std::vector<int>& S, int q) {
 }  // namespace
 
 diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<LocalGate>& gens,
-                            const std::vector<int>& diff, int n, SegmentPlan* out, bool forward) {
+                            const std::vector<int64_t>& dkey, int n, SegmentPlan* out, bool forward) {
   if (n < 3) return fail(DIAQ_ERR_UNSUPPORTED, "segment sweep needs n >= 3");
   SegmentPlan& P = *out;
   P = SegmentPlan();
@@ -338,6 +578,7 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
     std::vector<int> S;
     std::vector<int64_t> members;
     int ndots = 0;
+    int64_t pool_need = 0;
     for (; g != end; g += dir) {
       const LocalGate& L = lg[size_t(g)];
       std::vector<int> T;
@@ -346,32 +587,90 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
       std::vector<int> U = S;
       for (int q : T)
         if (std::find(U.begin(), U.end(), q) == U.end()) U.push_back(q);
-      const bool want_dot = !forward && diff[size_t(g)];
-      if (U.size() > 3 || int(members.size()) >= kSegMaxGates || (want_dot && ndots >= kSegMaxDots)) break;
+      const bool want_dot = !forward && dkey[size_t(g)] >= 0;
+      // LDS budget: entries (a run header at most every second member) and
+      // matrix doubles (diagonal gates counted at their complex size)
+      const int d = 1 << L.k;
+      const int64_t need = (is_diag(L) ? 2 * d : 2 * d * d) * (want_dot ? 2 : 1);
+      const int64_t entries = int64_t(members.size()) + 1;
+      if (U.size() > 3 || entries + entries / 2 + 1 > kSegLdsGates || pool_need + need > kSegLdsPool ||
+          (want_dot && ndots >= kSegMaxDots))
+        break;
       S = U;
       members.push_back(g);
+      pool_need += need;
       if (want_dot) ndots++;
     }
     pad_set(S, n);
     Segment seg;
     for (int j = 0; j < 3; j++) seg.S[j] = S[size_t(j)];
     seg.first = int64_t(P.gates.size());
+    seg.pool_lo = int64_t(P.pool.size());
     seg.ndots = 0;
     seg.dot_slot0 = int64_t(P.dot_gate.size());
-    for (int64_t m : members) {
+    auto push = [&](double re, double im) {
+      P.pool.push_back(re);
+      P.pool.push_back(im);
+    };
+    for (size_t mi = 0; mi < members.size();) {
+      // a run of >= 2 consecutive diagonal phase gates becomes one kRun
+      size_t mj = mi;
+      while (mj < members.size() && run_member(lg[size_t(members[mj])], gens[size_t(members[mj])],
+                                               !forward && dkey[size_t(members[mj])] >= 0))
+        mj++;
+      if (mj - mi >= 2) {
+        SegGate hd;
+        std::memset(&hd, 0, sizeof(hd));
+        hd.kind = kRun;
+        hd.b0 = int32_t(mj - mi);
+        hd.dot = -1;
+        P.gates.push_back(hd);
+        P.gate_of.push_back(members[mi]);
+        int64_t last_key = -1;
+        int last_dot = -1;
+        for (size_t x = mi; x < mj; x++) {
+          const int64_t m = members[x];
+          const LocalGate& L = lg[size_t(m)];
+          SegGate sg;
+          std::memset(&sg, 0, sizeof(sg));
+          sg.kind = kRunMember;
+          sg.cmask = L.cmask;
+          sg.dk = L.k;
+          for (int j = 0; j < L.k; j++) sg.q[j] = L.targets[j];
+          sg.dot = -1;
+          if (!forward && dkey[size_t(m)] >= 0) {
+            if (dkey[size_t(m)] == last_key) {
+              sg.dot = last_dot;
+            } else {
+              sg.dot = last_dot = seg.ndots++;
+              last_key = dkey[size_t(m)];
+              P.dot_gate.push_back(m);
+            }
+          }
+          sg.moff = int64_t(P.pool.size());
+          const int d = 1 << L.k;
+          for (int r = 0; r < d; r++) {
+            const double a = std::atan2(L.m[r][r][1], L.m[r][r][0]);
+            P.pool.push_back(forward ? a : -a);
+          }
+          if (sg.dot >= 0)
+            for (int r = 0; r < d; r++) P.pool.push_back(gens[size_t(m)].m[r][r][0]);
+          P.gates.push_back(sg);
+          P.gate_of.push_back(m);
+        }
+        mi = mj;
+        continue;
+      }
+      const int64_t m = members[mi++];
       const LocalGate& L = lg[size_t(m)];
       SegGate sg;
       std::memset(&sg, 0, sizeof(sg));
       sg.cmask = L.cmask;
-      sg.dot = (!forward && diff[size_t(m)]) ? seg.ndots++ : -1;
+      sg.dot = (!forward && dkey[size_t(m)] >= 0) ? seg.ndots++ : -1;
       if (sg.dot >= 0) P.dot_gate.push_back(m);
       P.gate_of.push_back(m);
       sg.moff = int64_t(P.pool.size());
       const int d = 1 << L.k;
-      auto push = [&](double re, double im) {
-        P.pool.push_back(re);
-        P.pool.push_back(im);
-      };
       if (is_diag(L)) {
         sg.kind = kDiag;
         sg.dk = L.k;
@@ -393,6 +692,7 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
           sg.b1 = local_bit(S, L.targets[1]);
         } else {
           sg.kind = kThree;
+          seg.three = true;
           // S-local index rs -> gate-local index
           for (int rs = 0; rs < 8; rs++) {
             int rg = 0;
@@ -415,6 +715,7 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
       P.gates.push_back(sg);
     }
     seg.ngates = int64_t(P.gates.size()) - seg.first;
+    seg.pool_n = int64_t(P.pool.size()) - seg.pool_lo;
     P.segs.push_back(seg);
   }
   return DIAQ_OK;
@@ -432,33 +733,13 @@ diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan&
   const int64_t ncos = (int64_t(1) << n) >> 3;
   const int64_t blocks = (ncos + kSegBlock - 1) / kSegBlock;
   for (const Segment& seg : P.segs) {
-    SegArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.ncos = ncos;
-    for (int j = 0; j < 3; j++) a.sorted[j] = seg.S[j];
-    for (int r = 0; r < 8; r++) {
-      int64_t o = 0;
-      for (int j = 0; j < 3; j++)
-        if ((r >> j) & 1) o |= int64_t(1) << seg.S[j];
-      a.off[r] = o;
-    }
-    a.ngates = int32_t(seg.ngates);
-    a.ndots = seg.ndots;
-    a.gates = dg + seg.first;
-    a.pool = dp;
-    if (P.forward) {
-      if (dt == DIAQ_C128)
-        hipLaunchKernelGGL((segment_kernel<double, false>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
-                           static_cast<double2*>(psi), nullptr, nullptr);
-      else
-        hipLaunchKernelGGL((segment_kernel<float, false>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
-                           static_cast<float2*>(psi), nullptr, nullptr);
-    } else if (dt == DIAQ_C128) {
-      hipLaunchKernelGGL((segment_kernel<double, true>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
-                         static_cast<double2*>(psi), static_cast<double2*>(lam), partial);
+    const SegArgs a = make_seg_args(seg, n, dg, dp);
+    if (dt == DIAQ_C128) {
+      if (seg.three) launch_segment<double, true>(P.forward, blocks, stream, a, psi, lam, partial);
+      else launch_segment<double, false>(P.forward, blocks, stream, a, psi, lam, partial);
     } else {
-      hipLaunchKernelGGL((segment_kernel<float, true>), dim3(unsigned(blocks)), dim3(kSegBlock), 0, stream, a,
-                         static_cast<float2*>(psi), static_cast<float2*>(lam), partial);
+      if (seg.three) launch_segment<float, true>(P.forward, blocks, stream, a, psi, lam, partial);
+      else launch_segment<float, false>(P.forward, blocks, stream, a, psi, lam, partial);
     }
     DIAQ_HIP(hipGetLastError());
     if (seg.ndots) {
@@ -492,6 +773,94 @@ size_t segment_pool_offset(const SegmentPlan& P) {
 int64_t segment_blocks(int n) {
   const int64_t ncos = (int64_t(1) << n) >> 3;
   return (ncos + kSegBlock - 1) / kSegBlock;
+}
+
+
+// ---------------------------------------------------------------------------
+// Grouped sweeps: step k runs segment k of every plan that has one, for all
+// states in one launch (and their dot sums in a second).
+// ---------------------------------------------------------------------------
+
+diaq_status_t build_grouped(const std::vector<GroupItem>& items, bool forward, GroupedSweep* out) {
+  GroupedSweep& G = *out;
+  G = GroupedSweep();
+  G.forward = forward;
+  size_t nsteps = 0;
+  for (const auto& it : items) nsteps = std::max(nsteps, it.plan->segs.size());
+  std::vector<GroupSeg> segs;
+  std::vector<GroupRed> reds;
+  for (size_t k = 0; k < nsteps; k++) {
+    GroupedStep st;
+    st.seg_first = int64_t(segs.size());
+    st.red_first = int64_t(reds.size());
+    int64_t blocks = 0, red_blocks = 0;
+    for (const auto& it : items) {
+      const SegmentPlan& P = *it.plan;
+      if (k >= P.segs.size()) continue;
+      const Segment& seg = P.segs[k];
+      const char* t = static_cast<const char*>(it.table);
+      const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
+      const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
+      GroupSeg g;
+      std::memset(&g, 0, sizeof(g));
+      g.a = make_seg_args(seg, it.n, reinterpret_cast<const SegGate*>(t), reinterpret_cast<const double*>(t + gb));
+      g.psi = it.psi;
+      g.lam = it.lam;
+      g.partial = it.partial;
+      g.block0 = blocks;
+      blocks += segment_blocks(it.n);
+      segs.push_back(g);
+      st.three = st.three || seg.three;
+      if (!forward && seg.ndots) {
+        GroupRed r;
+        std::memset(&r, 0, sizeof(r));
+        r.partial = it.partial;
+        r.blocks = segment_blocks(it.n);
+        r.ndots = seg.ndots;
+        r.slot = reinterpret_cast<const int64_t*>(t + gb + pb) + seg.dot_slot0;
+        r.red0 = red_blocks;
+        red_blocks += seg.ndots;
+        reds.push_back(r);
+      }
+    }
+    st.seg_count = int64_t(segs.size()) - st.seg_first;
+    st.red_count = int64_t(reds.size()) - st.red_first;
+    st.blocks = blocks;
+    st.red_blocks = red_blocks;
+    if (blocks > 0x7fffffffLL) return fail(DIAQ_ERR_UNSUPPORTED, "grouped step needs %lld workgroups", (long long)blocks);
+    G.steps.push_back(st);
+  }
+  const size_t sb = ((segs.size() * sizeof(GroupSeg) + 255) / 256) * 256;
+  G.red_offset = sb;
+  G.host.assign(sb + reds.size() * sizeof(GroupRed) + 256, 0);
+  if (!segs.empty()) std::memcpy(G.host.data(), segs.data(), segs.size() * sizeof(GroupSeg));
+  if (!reds.empty()) std::memcpy(G.host.data() + sb, reds.data(), reds.size() * sizeof(GroupRed));
+  return DIAQ_OK;
+}
+
+diaq_status_t run_grouped(hipStream_t stream, const GroupedSweep& G, double* dots) {
+  const GroupSeg* segs = static_cast<const GroupSeg*>(G.dev);
+  const GroupRed* reds = reinterpret_cast<const GroupRed*>(static_cast<const char*>(G.dev) + G.red_offset);
+  for (const GroupedStep& st : G.steps) {
+    if (!st.seg_count) continue;
+    const dim3 grid(unsigned(st.blocks)), block(kSegBlock);
+    const GroupSeg* l = segs + st.seg_first;
+    const int cnt = int(st.seg_count);
+    if (G.forward) {
+      if (st.three) hipLaunchKernelGGL((grouped_segment_kernel<double, false, true>), grid, block, 0, stream, l, cnt);
+      else hipLaunchKernelGGL((grouped_segment_kernel<double, false, false>), grid, block, 0, stream, l, cnt);
+    } else {
+      if (st.three) hipLaunchKernelGGL((grouped_segment_kernel<double, true, true>), grid, block, 0, stream, l, cnt);
+      else hipLaunchKernelGGL((grouped_segment_kernel<double, true, false>), grid, block, 0, stream, l, cnt);
+    }
+    DIAQ_HIP(hipGetLastError());
+    if (st.red_count) {
+      hipLaunchKernelGGL(grouped_reduce_kernel, dim3(unsigned(st.red_blocks)), dim3(256), 0, stream,
+                         reds + st.red_first, int(st.red_count), dots);
+      DIAQ_HIP(hipGetLastError());
+    }
+  }
+  return DIAQ_OK;
 }
 
 }  // namespace diaq
