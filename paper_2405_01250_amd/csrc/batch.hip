@@ -487,7 +487,7 @@ struct WideCirc {
 struct SegPatch {
   double* dst;
   int32_t rot;
-  int32_t diag;    // 1: the table holds the diagonal only; 2: the diagonal's phase angles
+  int32_t diag;    // 1: the table holds the diagonal only
   int32_t dim;     // 2 or 4
   int32_t dagger;  // 1: store U^dagger (reverse sweep)
   int64_t slot;    // theta index
@@ -503,9 +503,7 @@ __global__ void seg_patch_kernel(const SegPatch* __restrict__ patches, int64_t c
   double m[4][4][2];
   rot_matrix(p.rot, theta ? p.scale * theta[p.slot] : p.angle0, m);
   const double sg = p.dagger ? -1.0 : 1.0;
-  if (p.diag == 2) {
-    for (int r = 0; r < p.dim; r++) p.dst[r] = sg * atan2(m[r][r][1], m[r][r][0]);
-  } else if (p.diag) {
+  if (p.diag) {
     for (int r = 0; r < p.dim; r++) {
       p.dst[2 * r] = m[r][r][0];
       p.dst[2 * r + 1] = sg * m[r][r][1];
@@ -852,7 +850,7 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
           std::memset(&sp, 0, sizeof(sp));
           sp.rot = w.rot[size_t(m)];
           if (P->gates[i].kind == 4) continue;  // run header
-          sp.diag = P->gates[i].kind == 5 ? 2 : P->gates[i].kind == 3 ? 1 : 0;
+          sp.diag = (P->gates[i].kind == 5 || P->gates[i].kind == 3) ? 1 : 0;
           sp.dim = sp.diag ? (1 << P->gates[i].dk) : (P->gates[i].kind == 0 ? 2 : 4);
           sp.dagger = P->forward ? 0 : 1;
           sp.slot = circ[size_t(w.c)].p0 + w.pidx[size_t(m)];

@@ -224,19 +224,17 @@ __device__ __forceinline__ void flush_dot(double2 (*acc)[kSegBlock / 64], int j,
 // A run of m diagonal gates (the m entries after the header).  They commute,
 // so every dot may be taken at the start of the run, where it is
 // sum_i G(i) conj(lambda_i) psi_i (the generators are real and diagonal);
-// the phases add up as angles and are applied once.  Consecutive members
-// that share a dot slot (same parameter and scale) add into one dot.
+// the phases multiply into one factor per amplitude, applied once.
+// Consecutive members that share a dot slot (same parameter and scale) add
+// into one dot.
 template <bool LAM>
 __device__ __forceinline__ void apply_run(Coset& s, const SegArgs& a, int gi, int m, int64_t base,
                                           double2 (*acc)[kSegBlock / 64]) {
-  double ang[8], wr[8], wi[8];
+  double fr[8], fi[8];
 #pragma unroll
   for (int r = 0; r < 8; r++) {
-    ang[r] = 0.0;
-    if (LAM) {
-      wr[r] = s.lr[r] * s.pr[r] + s.li[r] * s.pi[r];
-      wi[r] = s.lr[r] * s.pi[r] - s.li[r] * s.pr[r];
-    }
+    fr[r] = 1.0;
+    fi[r] = 0.0;
   }
   int cur = -1;
   double dre = 0, dim = 0;
@@ -247,8 +245,8 @@ __device__ __forceinline__ void apply_run(Coset& s, const SegArgs& a, int gi, in
       cur = mg.dot;
       dre = dim = 0;
     }
-    const double* at = a.pool + mg.moff;
-    const double* gt = at + (1 << mg.dk);
+    const double* vt = a.pool + mg.moff;
+    const double* gt = vt + 2 * (1 << mg.dk);
 #pragma unroll
     for (int r = 0; r < 8; r++) {
       const uint64_t i = uint64_t(base + a.off[r]);
@@ -257,25 +255,28 @@ __device__ __forceinline__ void apply_run(Coset& s, const SegArgs& a, int gi, in
 #pragma unroll
       for (int j = 0; j < 3; j++)
         if (j < mg.dk) t |= int((i >> mg.q[j]) & 1) << j;
-      ang[r] += at[t];
+      const double vr = vt[2 * t], vi = vt[2 * t + 1];
+      const double x = fr[r] * vr - fi[r] * vi;
+      fi[r] = fr[r] * vi + fi[r] * vr;
+      fr[r] = x;
       if (LAM && mg.dot >= 0) {
+        // conj(lambda) psi, unchanged by the run's phases (recomputed here
+        // rather than held in registers)
         const double g = gt[t];
-        dre += g * wr[r];
-        dim += g * wi[r];
+        dre += g * (s.lr[r] * s.pr[r] + s.li[r] * s.pi[r]);
+        dim += g * (s.lr[r] * s.pi[r] - s.li[r] * s.pr[r]);
       }
     }
   }
   if (LAM && cur >= 0) flush_dot(acc, cur, dre, dim);
 #pragma unroll
   for (int r = 0; r < 8; r++) {
-    double sn, cs;
-    sincos(ang[r], &sn, &cs);
-    double x = cs * s.pr[r] - sn * s.pi[r];
-    s.pi[r] = cs * s.pi[r] + sn * s.pr[r];
+    double x = fr[r] * s.pr[r] - fi[r] * s.pi[r];
+    s.pi[r] = fr[r] * s.pi[r] + fi[r] * s.pr[r];
     s.pr[r] = x;
     if (LAM) {
-      x = cs * s.lr[r] - sn * s.li[r];
-      s.li[r] = cs * s.li[r] + sn * s.lr[r];
+      x = fr[r] * s.lr[r] - fi[r] * s.li[r];
+      s.li[r] = fr[r] * s.li[r] + fi[r] * s.lr[r];
       s.lr[r] = x;
     }
   }
@@ -386,7 +387,7 @@ __device__ __forceinline__ void segment_body(const SegArgs& ga, typename Vec<R>:
 }
 
 template <typename R, bool LAM, bool T3>
-__global__ __launch_bounds__(kSegBlock) void segment_kernel(SegArgs a, typename Vec<R>::V* __restrict__ psi,
+__global__ __launch_bounds__(kSegBlock, LAM ? 3 : 1) void segment_kernel(SegArgs a, typename Vec<R>::V* __restrict__ psi,
                                                             typename Vec<R>::V* __restrict__ lam,
                                                             double2* __restrict__ partial) {
   segment_body<R, LAM, T3>(a, psi, lam, partial, blockIdx.x);
@@ -403,7 +404,7 @@ struct GroupSeg {
 };
 
 template <typename R, bool LAM, bool T3>
-__global__ __launch_bounds__(kSegBlock) void grouped_segment_kernel(const GroupSeg* __restrict__ list, int count) {
+__global__ __launch_bounds__(kSegBlock, LAM ? 3 : 1) void grouped_segment_kernel(const GroupSeg* __restrict__ list, int count) {
   int lo = 0, hi = count - 1;  // last item with block0 <= blockIdx.x
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -546,8 +547,8 @@ void pad_set(std::vector<int>& S, int n) {
   std::sort(S.begin(), S.end());
 }
 
-// A diagonal gate that can join a run: its entries are pure phases (stored
-// as angles) and, when its dot is wanted, its generator is real.
+// A diagonal gate that can join a run: its entries are pure phases and,
+// when its dot is wanted, its generator is real.
 bool run_member(const LocalGate& L, const LocalGate& gen, bool dot) {
   if (!is_diag(L)) return false;
   for (int r = 0; r < (1 << L.k); r++) {
@@ -649,10 +650,7 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
           }
           sg.moff = int64_t(P.pool.size());
           const int d = 1 << L.k;
-          for (int r = 0; r < d; r++) {
-            const double a = std::atan2(L.m[r][r][1], L.m[r][r][0]);
-            P.pool.push_back(forward ? a : -a);
-          }
+          for (int r = 0; r < d; r++) push(L.m[r][r][0], forward ? L.m[r][r][1] : -L.m[r][r][1]);
           if (sg.dot >= 0)
             for (int r = 0; r < d; r++) P.pool.push_back(gens[size_t(m)].m[r][r][0]);
           P.gates.push_back(sg);
