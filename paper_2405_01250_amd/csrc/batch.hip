@@ -354,20 +354,22 @@ __device__ __forceinline__ int find_item(const WideVec* __restrict__ list, int c
 }
 
 __global__ __launch_bounds__(kObsBlock) void grouped_init_kernel(const WideVec* __restrict__ list, int count) {
+  using ND = Nat<double>::T;
   const WideVec& w = list[find_item(list, count)];
   const int64_t i = (int64_t(blockIdx.x) - w.block0) * kObsBlock + threadIdx.x;
-  if (i < w.N) w.psi[i] = double2{i == 0 ? 1.0 : 0.0, 0.0};
+  if (i < w.N) gptr(reinterpret_cast<ND*>(w.psi))[i] = ND{i == 0 ? 1.0 : 0.0, 0.0};
 }
 
 // lambda = H psi for the diagonal observable; one partial <psi|lambda> per
 // workgroup.
 __global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const WideVec* __restrict__ list, int count) {
+  using ND = Nat<double>::T;
   const WideVec& w = list[find_item(list, count)];
   const int64_t blk = int64_t(blockIdx.x) - w.block0;
-  const double2* __restrict__ psi = w.psi;
-  double2* __restrict__ lam = w.lam;
-  const uint64_t* __restrict__ zm = w.zm;
-  const double* __restrict__ coef = w.coef;
+  const auto* __restrict__ psi = gptr(reinterpret_cast<const ND*>(w.psi));
+  auto* __restrict__ lam = gptr(reinterpret_cast<ND*>(w.lam));
+  const auto* __restrict__ zm = gptr(w.zm);
+  const auto* __restrict__ coef = gptr(w.coef);
   const int64_t N = w.N;
   const int nt = w.nt;
   double re = 0, im = 0;
@@ -375,8 +377,8 @@ __global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const Wid
   if (i < N) {
     double h = 0;
     for (int t = 0; t < nt; t++) h += (__popcll(uint64_t(i) & zm[t]) & 1) ? -coef[t] : coef[t];
-    const double2 p = psi[i];
-    const double2 l{h * p.x, h * p.y};
+    const ND p = psi[i];
+    const ND l{h * p.x, h * p.y};
     lam[i] = l;
     re = p.x * l.x + p.y * l.y;
     im = p.x * l.y - p.y * l.x;
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const Wid
       t.x += wsum[q].x;
       t.y += wsum[q].y;
     }
-    w.partial[blk] = t;
+    gptr(reinterpret_cast<ND*>(w.partial))[blk] = ND{t.x, t.y};
   }
 }
 
@@ -403,10 +405,12 @@ __global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const Wid
 __global__ __launch_bounds__(256) void grouped_eval_kernel(const WideVec* __restrict__ list) {
   const WideVec& w = list[blockIdx.x];
   const int64_t nb = (w.N + kObsBlock - 1) / kObsBlock;
+  const auto* part = gptr(reinterpret_cast<const Nat<double>::T*>(w.partial));
   double re = 0, im = 0;
   for (int64_t b = threadIdx.x; b < nb; b += 256) {
-    re += w.partial[b].x;
-    im += w.partial[b].y;
+    const auto v = part[b];
+    re += v.x;
+    im += v.y;
   }
   for (int off = 32; off >= 1; off >>= 1) {
     re += __shfl_xor(re, off, 64);
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(256) void grouped_eval_kernel(const WideVec* __rest
       t.x += ws[q].x;
       t.y += ws[q].y;
     }
-    *w.eval = t;
+    gptr(reinterpret_cast<Nat<double>::T*>(w.eval))[0] = Nat<double>::T{t.x, t.y};
   }
 }
 

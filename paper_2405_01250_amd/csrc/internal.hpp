@@ -46,6 +46,28 @@ template <> struct Cx<float> { using V = float2; };
 
 inline size_t elem_bytes(diaq_dtype_t t) { return t == DIAQ_C128 ? 16 : 8; }
 
+// Pointers that arrive through memory (the grouped launches' descriptors)
+// are generic; casting them to the global address space keeps their
+// accesses off the flat path (whose waits would also stall on LDS reads)
+// and lets uniform reads use scalar loads.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+
+// Native two-element vectors (the element type of interleaved complex
+// arrays) for loads and stores through global-space pointers.
+template <typename R>
+struct Nat;
+template <>
+struct Nat<double> {
+  typedef double T __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Nat<float> {
+  typedef float T __attribute__((ext_vector_type(2)));
+};
+
 // ---------------------------------------------------------------------------
 // Objects behind the opaque handles
 // ---------------------------------------------------------------------------
