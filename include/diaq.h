@@ -284,9 +284,13 @@ diaq_status_t diaq_expect(diaq_ctx_t ctx, diaq_dia_t H, const void* psi,
  * conjugate-transposed DiaQ matrix of the same expansion).  `work` holds
  * 3 * 2^n elements of device memory.  Writes *expval and grad[0..nparams)
  * (host, zeroed first).  plan == NULL (or kron == 0): every gate and every
- * U^dagger is expanded and applied by Alg. 2; plan->kron: gates are applied
- * in place by Alg. 3 and each reverse step is one fused pass (dot, then
- * both vectors stepped back).  Synchronises the stream. */
+ * U^dagger is expanded and applied by Alg. 2; plan->kron: the forward pass
+ * runs fused Alg. 3 operations in place (max_fused_qubits, default 3) and
+ * the reverse sweep is cut into segments of consecutive gates whose
+ * non-diagonal targets fit in 3 qubits, each segment one pass over psi and
+ * lambda replaying its gates per coset in exact reverse order (dots taken
+ * before each gate is undone; n < 3 falls back to one pass per gate).
+ * Synchronises the stream. */
 diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                 int64_t ngates, int32_t nqubits,
                                 diaq_dtype_t dtype, diaq_dia_t H,
