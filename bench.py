@@ -227,7 +227,9 @@ def main():
         out["variants"] = [fused_extra(D, gates, state, scratch, ctx, n, a.steps, **kw)
                            for kw in ({"fuse": True, "max_fused_qubits": 2}, {"fuse": True, "max_fused_qubits": 3},
                                       {"kron": True}, {"kron": True, "fuse": True, "max_fused_qubits": 2},
-                                      {"kron": True, "fuse": True, "max_fused_qubits": 3})]
+                                      {"kron": True, "fuse": True, "max_fused_qubits": 3},
+                                      {"kron": True, "fuse": True, "max_fused_qubits": 4},
+                                      {"kron": True, "fuse": True, "max_fused_qubits": 5})]
         out["tfim"] = tfim_extra(D, W, torch, ctx, state, scratch, tdt)
         out["matrix"] = matrix_extra(D, W)
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
@@ -279,7 +281,8 @@ def tfim_extra(D, W, torch, ctx, state, scratch, tdt):
            "gates": len(gates), "plans": []}
     mags = []
     for kw in ({}, {"fuse": True, "max_fused_qubits": 3}, {"kron": True},
-               {"kron": True, "fuse": True, "max_fused_qubits": 3}):
+               {"kron": True, "fuse": True, "max_fused_qubits": 3},
+               {"kron": True, "fuse": True, "max_fused_qubits": 5}):
         plan = D.make_plan(**kw) if kw else None
         nops, nbytes = D.plan_count(gates, n, plan, dtype=tdt)
         for _ in range(2):  # the first run sizes the workspaces; the second is timed

@@ -267,6 +267,14 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       std::vector<FusedOp> ops;
       double bytes = 0, maxb = 0;
       int64_t nops = 0;
+      if (kron && fuse && k > 3) {
+        std::vector<BigOp> big;
+        DIAQ_TRY(plan_big(gates, ngates, n, k, &big));
+        nops = int64_t(big.size());
+        bytes = double(nops) * 2.0 * s * N;
+        cands.push_back(Cand{p, bytes / (rate_kron * 1e6) + double(nops) * launch_ms, 0.0});
+        return DIAQ_OK;
+      }
       if (fuse) {
         DIAQ_TRY(plan_fusion(gates, ngates, n, k, dtype, &ops, kron != 0));
       } else {
@@ -295,7 +303,7 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
     for (int k = 1; k <= 3; k++) DIAQ_TRY(add(1, k, 0));
     if (allow_kron) {
       DIAQ_TRY(add(0, 0, 1));
-      for (int k = 1; k <= 3; k++) DIAQ_TRY(add(1, k, 1));
+      for (int k = 1; k <= 5; k++) DIAQ_TRY(add(1, k, 1));
     }
     size_t free_b = 0, total_b = 0;
     DIAQ_HIP(hipMemGetInfo(&free_b, &total_b));

@@ -205,7 +205,13 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
     void* res = nullptr;
     diaq_status_t st;
     const int kmax = plan && plan->max_fused_qubits ? plan->max_fused_qubits : 2;
-    if (plan && plan->kron) {
+    if (plan && plan->kron && plan->fuse && kmax > 3) {
+      // groups of four or five qubits: dense local matrices
+      std::vector<BigOp> ops;
+      st = plan_big(gates + begin, end - begin, nqubits, kmax, &ops);
+      if (st == DIAQ_OK) st = run_big(ctx, ops, nqubits, dtype, state);
+      res = state;
+    } else if (plan && plan->kron) {
       std::vector<FusedOp> ops;
       if (plan->fuse) {
         st = plan_fusion(gates + begin, end - begin, nqubits, kmax, dtype, &ops, true);
@@ -244,7 +250,12 @@ diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates, int32_t 
     const double s = double(elem_bytes(dtype)), N = double(int64_t(1) << nqubits);
     double b = 0;
     int64_t count = 0;
-    if (plan && plan->kron) {
+    if (plan && plan->kron && plan->fuse && plan->max_fused_qubits > 3) {
+      std::vector<BigOp> ops;
+      DIAQ_TRY(plan_big(gates, ngates, nqubits, plan->max_fused_qubits, &ops));
+      count = int64_t(ops.size());
+      b = double(count) * 2.0 * s * N;  // every operation reads and writes the state once
+    } else if (plan && plan->kron) {
       if (plan->fuse) {
         std::vector<FusedOp> ops;
         DIAQ_TRY(plan_fusion(gates, ngates, nqubits, plan->max_fused_qubits ? plan->max_fused_qubits : 2, dtype,
@@ -316,10 +327,16 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     // forward: psi = U psi0 (Alg. 3 plan: fused in-place operations)
     DIAQ_HIP(hipMemcpyAsync(psi, psi0, vb, hipMemcpyDeviceToDevice, ctx->stream));
     if (kron) {
-      std::vector<FusedOp> ops;
-      const int kmax = plan->max_fused_qubits > 0 ? std::min(plan->max_fused_qubits, 3) : 3;
-      DIAQ_TRY(plan_fusion(gates, ngates, nqubits, kmax, dtype, &ops, true));
-      DIAQ_TRY(run_kron(ctx, ops, nqubits, dtype, psi));
+      const int kmax = plan->max_fused_qubits > 0 ? plan->max_fused_qubits : 4;
+      if (kmax > 3) {
+        std::vector<BigOp> ops;
+        DIAQ_TRY(plan_big(gates, ngates, nqubits, kmax, &ops));
+        DIAQ_TRY(run_big(ctx, ops, nqubits, dtype, psi));
+      } else {
+        std::vector<FusedOp> ops;
+        DIAQ_TRY(plan_fusion(gates, ngates, nqubits, kmax, dtype, &ops, true));
+        DIAQ_TRY(run_kron(ctx, ops, nqubits, dtype, psi));
+      }
     } else {
       void* res = nullptr;
       DIAQ_TRY(run_plain(ctx, p, 0, ngates, nqubits, dtype, psi, tmp, &res));

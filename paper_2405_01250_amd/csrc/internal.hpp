@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <cstdio>
@@ -173,6 +174,25 @@ struct FusedOp {
 // each, whatever their diagonals), so any merge within kmax qubits pays.
 diaq_status_t plan_fusion(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, diaq_dtype_t dt,
                           std::vector<FusedOp>* ops, bool kron = false);
+
+// Alg. 3 operations of up to five qubits (kronbig.hip): a dense matrix on
+// the sorted qubits q (bit j of a local index is q[j]; controls are qubits
+// of the group), then diagonal row factors.  A gate of more than five
+// qubits with its controls stays raw (its LocalGate).
+struct BigOp {
+  int k = 0;
+  int q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<std::complex<double>> m;
+  std::vector<DiagFactor> post;
+  uint64_t mask = 0;
+  int64_t ngates = 0;
+  bool raw = false;
+  LocalGate lg;
+};
+diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops);
+// Applies the operations in place (each one read and one write of the
+// state), with profiling intervals of 2 s N bytes per operation.
+diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_dtype_t dt, void* state);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (one .hip file each)

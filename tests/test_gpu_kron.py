@@ -97,3 +97,56 @@ def test_kron_adjoint_controlled_and_two_qubit_rotations():
     fd = orc.fd_grad(psi0, n, gates, terms, pidx, h=1e-4)
     assert np.max(np.abs(g - fd)) <= 1e-7 * max(1.0, np.max(np.abs(fd)))
     assert np.max(np.abs(g - g2)) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# Groups of four and five qubits (dense local matrices)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kmax", [4, 5])
+@pytest.mark.parametrize("seed", range(5))
+def test_kron_big_groups_random_circuits(kmax, seed):
+    rng = np.random.default_rng(1900 + seed)
+    n = int(rng.integers(3, 14))
+    gates = [_random_gate(rng, n) for _ in range(int(rng.integers(20, 80)))]
+    if n >= 6:  # a gate of six qubits with its controls stays as it is
+        q = [int(v) for v in rng.permutation(n)[:6]]
+        m = np.linalg.qr(rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8)))[0]
+        gates.insert(len(gates) // 2, W.Gate("MATRIX", tuple(q[:3]), tuple(q[3:]), matrix=m))
+    x = W.random_state(n, seed)
+    plan = D.make_plan(kron=True, fuse=True, max_fused_qubits=kmax)
+    nops, _ = D.plan_count(gates, n, plan)
+    n3, _ = D.plan_count(gates, n, D.make_plan(kron=True, fuse=True, max_fused_qubits=3))
+    assert nops <= len(gates)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi, plan=plan)
+    assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "kmax=%d seed %d" % (kmax, seed))
+
+
+@pytest.mark.parametrize("kmax", [4, 5])
+def test_kron_big_groups_workloads(kmax):
+    plan = D.make_plan(kron=True, fuse=True, max_fused_qubits=kmax)
+    cases = [("qft", 16, W.qft(16), W.random_state(16, 2)),
+             ("random_layered", 20, W.random_layered(20, 4, 5), W.zero_state(20)),
+             ("tfim", 14, W.tfim(14, 6, 0.1), W.random_state(14, 6)),
+             ("hea", 12, W.hea(12, 3, 9)[0], W.zero_state(12)),
+             ("ghz", 12, W.ghz(12), W.zero_state(12))]
+    for name, n, gates, x in cases:
+        psi = to_dev(x)
+        D.apply_circuit(gates, psi, plan=plan)
+        assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "%s kmax=%d" % (name, kmax))
+    # fewer operations than three-qubit groups on the layered circuit
+    g = W.random_layered(28, 20, 28)
+    n3, _ = D.plan_count(g, 28, D.make_plan(kron=True, fuse=True, max_fused_qubits=3))
+    nk, _ = D.plan_count(g, 28, plan)
+    assert nk < n3
+
+
+def test_kron_big_groups_complex64():
+    n = 18
+    gates = W.random_layered(n, 3, 8) + W.qft(n)[:40]
+    x = W.random_state(n, 8)
+    ref = orc.apply_circuit(x, n, gates)
+    psi = to_dev(x, torch.complex64)
+    D.apply_circuit(gates, psi, plan=D.make_plan(kron=True, fuse=True, max_fused_qubits=5))
+    assert_state_close(to_host(psi), ref, TOL32, "kmax=5 c64", l2tol=1e-4)
