@@ -45,8 +45,9 @@ def _args():
     ap.add_argument("--extras", type=int, default=1, help="also time adjoint vs parameter shift (HEA n=20)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of autotuned product-kernel knobs (read if it holds this size, else written)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
-                    help="copy: run a plain device copy of 2^n complex elements (counter calibration)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "sweep"],
+                    help="copy: run a plain device copy of 2^n complex elements (counter calibration); "
+                         "sweep: single-gate expansion + SpMV rates per target qubit (one JSON line per gate)")
     return ap.parse_args()
 
 
@@ -116,6 +117,47 @@ def cpu_baseline(n, gates, budget_s, bytes_of_gate):
                       "as value" % (done, len(gates), n)}
 
 
+def sweep_mode(a):
+    """Single-gate sweep at 2^n amplitudes: for each gate shape and target
+    qubit, expansion and SpMV rates from HIP events (algorithmic bytes:
+    s*E written by the expansion, s*(E + 2N) moved by the product)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_01250_amd import diaq as D
+    from paper_2405_01250_amd import inputs as W
+
+    n = a.n
+    rng = np.random.default_rng(a.seed)
+    ctx = D.context()
+    for dt_name, tdt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        psi = torch.from_numpy(W.random_state(n, a.seed)).to("cuda:0").to(tdt)
+        scratch = torch.empty_like(psi)
+        D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
+        shapes = [("U3", lambda q: W.u3(*rng.uniform(0, 2 * math.pi, 3), q)),
+                  ("CX", lambda q: W.cx(0, q) if q else W.cx(1, 0)),
+                  ("RZ", lambda q: W.Gate("RZ", (q,), (), (0.7,))),
+                  ("CZ", lambda q: W.Gate("Z", (q,), (0 if q else 1,))),
+                  ("SWAP", lambda q: W.swap(q, n - 1 - q) if q != n - 1 - q else W.swap(q, 0))]
+        for name, make in shapes:
+            for q in range(n):
+                g = [make(q)]
+                arr = D.gate_array(g)
+                D.apply_circuit(g, psi, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
+                torch.cuda.synchronize()
+                D.profile_start(ctx)
+                for _ in range(a.steps):
+                    D.apply_circuit(g, psi, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
+                p = D.profile_stop(ctx)
+                out = {"mode": "sweep", "dtype": dt_name, "n": n, "gate": name, "q": q,
+                       "spmv_us": round(p["spmv_ms"] / max(1, p["spmv_launches"]) * 1e3, 1),
+                       "spmv_GBps": round(p["spmv_bytes"] / p["spmv_ms"] / 1e6, 1) if p["spmv_ms"] else None,
+                       "expand_GBps": round(p["expand_bytes"] / p["expand_ms"] / 1e6, 1) if p["expand_ms"] else None}
+                print(json.dumps(out), flush=True)
+        del psi, scratch
+        torch.cuda.empty_cache()
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -124,6 +166,9 @@ def main():
         sys.exit(2)
     if a.mode == "copy":
         copy_mode(a)
+        return
+    if a.mode == "sweep":
+        sweep_mode(a)
         return
     import numpy as np
     import torch
