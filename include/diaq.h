@@ -362,6 +362,9 @@ typedef struct diaq_tuning {
   int32_t diag_pad;        /* elements of padding between the expanded
                               diagonals in the circuit workspace (-1: none) */
   int32_t reserved[1];
+  uint64_t spmv_group_qubits; /* when non-zero, bit q says whether tiles are
+                              paired across coupling qubit q (a per-qubit
+                              choice that replaces spmv_group_min_qubit) */
 } diaq_tuning_t;
 
 diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);
@@ -373,8 +376,10 @@ diaq_status_t diaq_get_tuning(diaq_ctx_t ctx, diaq_tuning_t* t);
 
 /* Pick the product kernel's knobs for 2^nqubits-element vectors: time the
  * DiaQ SpMV of expanded one-qubit gates on qubits spread over the register
- * (and a CX) under every candidate tuning, keep the fastest, install it in
- * the context and write it to *out.  With cache_path (a JSON file) the
+ * (and a CX) under every candidate tuning, keep the fastest, then decide
+ * tile pairing qubit by qubit (a U3 on each qubit from the tile size up,
+ * timed paired and unpaired), install the result in the context and write
+ * it to *out.  With cache_path (a JSON file) the
  * result is stored under a key naming the device, n and dtype, and a
  * later call with the same key reads it back without timing.  Allocates
  * and frees its own test vectors.  Synchronises the stream. */

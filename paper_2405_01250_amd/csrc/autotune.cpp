@@ -55,6 +55,14 @@ std::string read_file(const char* path) {
   return s;
 }
 
+bool u64_field(const std::string& obj, const char* name, uint64_t* v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  size_t p = obj.find(pat);
+  if (p == std::string::npos) return false;
+  *v = std::strtoull(obj.c_str() + p + pat.size(), nullptr, 10);
+  return true;
+}
+
 bool int_field(const std::string& obj, const char* name, int32_t* v) {
   const std::string pat = std::string("\"") + name + "\":";
   size_t p = obj.find(pat);
@@ -76,6 +84,7 @@ bool cache_lookup(const char* path, const std::string& key, diaq_tuning_t* t) {
   bool ok = int_field(obj, "spmv_rows", &r.spmv_rows) && int_field(obj, "spmv_group_bits", &r.spmv_group_bits) &&
             int_field(obj, "spmv_chunk", &r.spmv_chunk) && int_field(obj, "spmv_nontemporal", &r.spmv_nontemporal) &&
             int_field(obj, "spmv_group_min_qubit", &r.spmv_group_min_qubit);
+  if (ok) u64_field(obj, "spmv_group_qubits", &r.spmv_group_qubits);
   if (ok) *t = r;
   return ok;
 }
@@ -96,9 +105,9 @@ diaq_status_t cache_store(const char* path, const std::string& key, const diaq_t
   char buf[512];
   std::snprintf(buf, sizeof(buf),
                 "{\"key\":\"%s\",\"spmv_rows\":%d,\"spmv_group_bits\":%d,\"spmv_chunk\":%d,"
-                "\"spmv_nontemporal\":%d,\"spmv_group_min_qubit\":%d,\"ms\":%.4f}",
+                "\"spmv_nontemporal\":%d,\"spmv_group_min_qubit\":%d,\"spmv_group_qubits\":%llu,\"ms\":%.4f}",
                 key.c_str(), t.spmv_rows, t.spmv_group_bits, t.spmv_chunk, t.spmv_nontemporal,
-                t.spmv_group_min_qubit, ms);
+                t.spmv_group_min_qubit, (unsigned long long)t.spmv_group_qubits, ms);
   lines.push_back(buf);
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "wb");
@@ -232,6 +241,55 @@ diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype,
     for (size_t c = 1; c < cand.size(); c++)
       if (total[c] < total[bi]) bi = c;
     best = cand[bi];
+    // tile pairing qubit by qubit: a U3 on q, timed paired and unpaired
+    // (partner rows 2^q apart meet in the caches for some q and not others)
+    const int tile_log2 = 8 + (best.spmv_rows == 4 ? 2 : best.spmv_rows == 2 ? 1 : 0);
+    if (n > tile_log2 + 1) {
+      uint64_t mask = 0;
+      for (int q = tile_log2; q < n; q++) {
+        diaq_gate_t g{};
+        g.kind = DIAQ_GATE_U3;
+        g.ntargets = 1;
+        g.targets[0] = q;
+        g.params[0] = 0.3;
+        g.params[1] = 0.5;
+        g.params[2] = 0.7;
+        g.param_index = -1;
+        LocalGate lg;
+        DIAQ_TRY(local_gate(&g, n, &lg));
+        const std::vector<int64_t> offs = gate_offsets(lg);
+        const std::vector<int64_t> st = packing_starts(offs, n);
+        DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(st.back()) * s));
+        DIAQ_TRY(launch_expand(ctx, lg, n, dtype, offs, st, ctx->diag.ptr));
+        SpmvOp op;
+        op.n = n;
+        op.dtype = dtype;
+        op.nd = int(offs.size());
+        op.host_off = offs.data();
+        op.host_start = st.data();
+        op.values = ctx->diag.ptr;
+        op.qubit_mask = lg.tmask;
+        double ms2[2] = {0, 0};
+        for (int paired = 0; paired < 2; paired++) {
+          diaq_tuning_t t = best;
+          t.spmv_group_bits = paired ? 1 : -1;
+          t.spmv_group_qubits = uint64_t(1) << q;
+          ctx->tuning = t;
+          DIAQ_TRY(launch_spmv(ctx, op, x, y));  // warm-up
+          DIAQ_HIP(hipEventRecord(tm.a, ctx->stream));
+          for (int r = 0; r < 2 * reps; r++) DIAQ_TRY(launch_spmv(ctx, op, x, y));
+          DIAQ_HIP(hipEventRecord(tm.b, ctx->stream));
+          DIAQ_HIP(hipEventSynchronize(tm.b));
+          float ms = 0;
+          DIAQ_HIP(hipEventElapsedTime(&ms, tm.a, tm.b));
+          ms2[paired] = ms;
+        }
+        if (ms2[1] < 0.98 * ms2[0]) mask |= uint64_t(1) << q;  // a clear win only
+      }
+      best.spmv_group_bits = 0;
+      // a mask of zero means "no per-qubit choice": keep one unused high bit
+      best.spmv_group_qubits = mask ? mask : (uint64_t(1) << 63);
+    }
     best.expand_nontemporal = saved.expand_nontemporal;
     best.diag_pad = saved.diag_pad;
     ctx->tuning = best;

@@ -412,8 +412,14 @@ Plan plan_rows(const SpmvOp& op, const diaq_tuning_t& t, int rpt_override) {
   int bits[64], nb = 0;
   const int qmin =
       std::max(tile_log2, t.spmv_group_min_qubit > 0 ? t.spmv_group_min_qubit : kDefaultGroupMinQubit);
-  for (int q = n - 1; q >= qmin && nb < max_bits; q--)
-    if ((op.qubit_mask >> q) & 1) bits[nb++] = q;
+  if (t.spmv_group_qubits) {
+    // per-qubit choice (autotuned): pair across the chosen coupling qubits
+    for (int q = n - 1; q >= tile_log2 && nb < max_bits; q--)
+      if (((op.qubit_mask & t.spmv_group_qubits) >> q) & 1) bits[nb++] = q;
+  } else {
+    for (int q = n - 1; q >= qmin && nb < max_bits; q--)
+      if ((op.qubit_mask >> q) & 1) bits[nb++] = q;
+  }
   // at most 4 rows per lane: larger groups take fewer rows per tile
   while ((rpt << nb) > 4 && rpt > 1) {
     rpt >>= 1;

@@ -109,3 +109,31 @@ def test_create_without_gpu_fails_loudly(lib):
     assert st != 0
     with pytest.raises(RuntimeError):
         D.context()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct the binding passes by pointer has the header's size and
+    field offsets (a C program built from include/diaq.h prints them)."""
+    structs = {"diaq_gate_t": D.diaq_gate_t, "diaq_plan_t": D.diaq_plan_t, "diaq_tuning_t": D.diaq_tuning_t,
+               "diaq_profile_t": D.diaq_profile_t, "diaq_circuit_t": D.diaq_circuit_t,
+               "diaq_chain_step_t": D.diaq_chain_step_t}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "diaq.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            name, field, value = line.split()
+            got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
