@@ -328,6 +328,11 @@ __global__ void batch_reset_kernel(int32_t* queue, double* expvals, int64_t nc, 
 constexpr int kWideMinQubits = 15;
 constexpr int kSideStreams = 1;  // the persistent kernel runs beside the wide steps
 constexpr int kObsBlock = 256;
+// amplitudes per lane in the grouped init / observable grids: enough work per
+// workgroup to amortise the search for its circuit (N >= 2^15 is a multiple
+// of the 4096 amplitudes a workgroup covers)
+constexpr int kObsPerLane = 16;
+constexpr int64_t kObsSpan = int64_t(kObsBlock) * kObsPerLane;
 
 // One wide circuit's vectors for the grouped init / observable kernels.
 struct WideVec {
@@ -340,7 +345,7 @@ struct WideVec {
   int32_t pad;
   double2* partial;
   double2* eval;
-  int64_t block0;  // first workgroup of this circuit in the grouped grid (N / kObsBlock each)
+  int64_t block0;  // first workgroup of this circuit in the grouped grid (N / kObsSpan each)
 };
 
 __device__ __forceinline__ int find_item(const WideVec* __restrict__ list, int count) {
@@ -356,8 +361,13 @@ __device__ __forceinline__ int find_item(const WideVec* __restrict__ list, int c
 __global__ __launch_bounds__(kObsBlock) void grouped_init_kernel(const WideVec* __restrict__ list, int count) {
   using ND = Nat<double>::T;
   const WideVec& w = list[find_item(list, count)];
-  const int64_t i = (int64_t(blockIdx.x) - w.block0) * kObsBlock + threadIdx.x;
-  if (i < w.N) gptr(reinterpret_cast<ND*>(w.psi))[i] = ND{i == 0 ? 1.0 : 0.0, 0.0};
+  const int64_t i0 = (int64_t(blockIdx.x) - w.block0) * kObsSpan + threadIdx.x;
+  auto* psi = gptr(reinterpret_cast<ND*>(w.psi));
+#pragma unroll
+  for (int e = 0; e < kObsPerLane; e++) {
+    const int64_t i = i0 + int64_t(e) * kObsBlock;
+    if (i < w.N) psi[i] = ND{i == 0 ? 1.0 : 0.0, 0.0};
+  }
 }
 
 // lambda = H psi for the diagonal observable; one partial <psi|lambda> per
@@ -373,15 +383,16 @@ __global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const Wid
   const int64_t N = w.N;
   const int nt = w.nt;
   double re = 0, im = 0;
-  const int64_t i = blk * kObsBlock + threadIdx.x;
-  if (i < N) {
+  for (int e = 0; e < kObsPerLane; e++) {
+    const int64_t i = blk * kObsSpan + int64_t(e) * kObsBlock + threadIdx.x;
+    if (i >= N) break;
     double h = 0;
     for (int t = 0; t < nt; t++) h += (__popcll(uint64_t(i) & zm[t]) & 1) ? -coef[t] : coef[t];
     const ND p = psi[i];
     const ND l{h * p.x, h * p.y};
     lam[i] = l;
-    re = p.x * l.x + p.y * l.y;
-    im = p.x * l.y - p.y * l.x;
+    re += p.x * l.x + p.y * l.y;
+    im += p.x * l.y - p.y * l.x;
   }
   for (int off = 32; off >= 1; off >>= 1) {
     re += __shfl_xor(re, off, 64);
@@ -404,7 +415,7 @@ __global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const Wid
 // in a fixed order.
 __global__ __launch_bounds__(256) void grouped_eval_kernel(const WideVec* __restrict__ list) {
   const WideVec& w = list[blockIdx.x];
-  const int64_t nb = (w.N + kObsBlock - 1) / kObsBlock;
+  const int64_t nb = (w.N + kObsSpan - 1) / kObsSpan;
   const auto* part = gptr(reinterpret_cast<const Nat<double>::T*>(w.partial));
   double re = 0, im = 0;
   for (int64_t b = threadIdx.x; b < nb; b += 256) {
@@ -786,7 +797,7 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
       // partial sums: the observable's, and the reverse sweep's per-segment dots
       int32_t maxdots = 1;
       for (const auto& sg : w.rev.segs) maxdots = std::max(maxdots, sg.ndots);
-      w.npart = std::max<int64_t>(((int64_t(1) << w.n) + kObsBlock - 1) / kObsBlock, segment_blocks(w.n) * maxdots);
+      w.npart = std::max<int64_t>(((int64_t(1) << w.n) + kObsSpan - 1) / kObsSpan, segment_blocks(w.n) * maxdots);
       w.o_part = part_bytes;
       part_bytes += (size_t(w.npart) * sizeof(double2) + 255) / 256 * 256;
       std::vector<int64_t> slots(w.rev.dot_gate.size());
@@ -936,7 +947,7 @@ diaq_status_t diaq_batch_create(diaq_ctx_t ctx, const diaq_circuit_t* circuits, 
         v.partial = part;
         v.eval = b->d_evals + x;
         v.block0 = blocks;
-        blocks += (N + kObsBlock - 1) / kObsBlock;
+        blocks += (N + kObsSpan - 1) / kObsSpan;
         wv.push_back(v);
       }
       DIAQ_TRY_BAIL(build_grouped(fi, true, &b->gfwd));
