@@ -275,6 +275,8 @@ def main():
                                       {"kron": True, "fuse": True, "max_fused_qubits": 3},
                                       {"kron": True, "fuse": True, "max_fused_qubits": 4},
                                       {"kron": True, "fuse": True, "max_fused_qubits": 5})]
+        if a.dtype == "c128":
+            out["c64"] = c64_extra(D, W, torch, gates, a.steps)
         out["tfim"] = tfim_extra(D, W, torch, ctx, state, scratch, tdt)
         out["matrix"] = matrix_extra(D, W)
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
@@ -311,6 +313,37 @@ def fused_extra(D, gates, state, scratch, ctx, n, steps, **kw):
             "product_GBps": round(prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9, 1) if prof["spmv_ms"] else None,
             "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)
             if prof["expand_ms"] else None}
+
+
+def c64_extra(D, W, torch, gates, steps):
+    """The same circuit on the plain path in complex64 (8-byte amplitudes):
+    gates/s and the kernels' rates, with the autotuned knobs for complex64
+    (the complex128 knobs are restored afterwards)."""
+    n = max(max(g.targets + tuple(g.controls)) for g in gates) + 1
+    ctx = D.context()
+    saved = D.get_tuning(ctx)
+    D.autotune(n, dtype=torch.complex64, ctx=ctx)
+    psi = torch.zeros(1 << n, dtype=torch.complex64, device="cuda:0")
+    psi[0] = 1
+    scratch = torch.empty_like(psi)
+    arr = D.gate_array(gates)
+    D.apply_circuit(gates, psi, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    D.profile_start(ctx)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        D.apply_circuit(gates, psi, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    p = D.profile_stop(ctx)
+    norm = float(torch.linalg.vector_norm(psi.to(torch.complex128)).item())
+    D.set_tuning(ctx, **saved)
+    del psi, scratch
+    torch.cuda.empty_cache()
+    return {"workload": "random layered n=%d, %d gates, complex64, plain path" % (n, len(gates)),
+            "gates_per_s": round(len(gates) * steps / dt, 2), "ms_per_step": round(dt / steps * 1e3, 1),
+            "spmv_GBps": round(p["spmv_bytes"] / p["spmv_ms"] / 1e6, 1),
+            "expand_GBps": round(p["expand_bytes"] / p["expand_ms"] / 1e6, 1), "final_norm": norm}
 
 
 def tfim_extra(D, W, torch, ctx, state, scratch, tdt):

@@ -12,8 +12,8 @@ namespace diaq {
 namespace {
 
 constexpr int kBlock = 256;
-// One element per lane: measured faster for this write stream than several
-// elements per lane a block apart (6.8 vs 5.9 TB/s at n = 28).
+// Pauli-sum diagonals: one element per lane (several elements per lane a
+// block apart measured slower for this write stream).
 constexpr int kPerThread = 1;
 
 template <typename R>
@@ -54,9 +54,46 @@ __device__ __forceinline__ void put(V* p, const V& v) {
   }
 }
 
+// Element t of diagonal d (row i = t + max(0, -d), column j = i + d) of the
+// expanded gate, times the folded diagonal factors of row i.
+__device__ __forceinline__ void expanded_element(const ExpandArgs& a, const double (*sm)[2], int dim, int64_t d,
+                                                 int64_t row0, int64_t t, double& vr, double& vi) {
+  const uint64_t i = uint64_t(t + row0);
+  const uint64_t j = uint64_t(int64_t(i) + d);
+  vr = 0;
+  vi = 0;
+  if (((i ^ j) & ~a.tmask) == 0) {
+    if ((i & a.cmask) != a.cmask) {
+      vr = (i == j) ? 1.0 : 0.0;
+    } else {
+      int r = 0, c = 0;
+      for (int b = 0; b < a.k; b++) {
+        r |= int((i >> a.targets[b]) & 1) << b;
+        c |= int((j >> a.targets[b]) & 1) << b;
+      }
+      vr = sm[r * dim + c][0];
+      vi = sm[r * dim + c][1];
+    }
+  }
+  // folded diagonal gates D after the core: (D A)[i, j] = D(i) A[i, j]
+  for (int f = 0; f < a.nf; f++) {
+    const DiagFactor& fa = a.factors[f];
+    int r = 0;
+    for (int b = 0; b < fa.k; b++) r |= int((i >> fa.q[b]) & 1) << b;
+    const double fr = fa.v[r][0], fi = fa.v[r][1];
+    const double nr = vr * fr - vi * fi;
+    vi = vr * fi + vi * fr;
+    vr = nr;
+  }
+}
+
+// One lane per element for complex128 (16-byte stores); two consecutive
+// elements per lane for complex64, stored as one 16-byte write when the pair
+// is 16-byte aligned.
 template <typename R, bool NT>
 __global__ __launch_bounds__(kBlock) void expand_kernel(ExpandArgs a, typename Vec<R>::V* __restrict__ out) {
   using V = typename Vec<R>::V;
+  constexpr int EPL = sizeof(R) == 4 ? 2 : 1;
   __shared__ double sm[64][2];
   const int dim = 1 << a.k;
   for (int t = threadIdx.x; t < dim * dim; t += kBlock) {
@@ -69,39 +106,22 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(ExpandArgs a, typename V
   const int64_t len = a.N - (d < 0 ? -d : d);
   const int64_t row0 = d < 0 ? -d : 0;
   V* dst = out + a.start[kd];
-  const int64_t t0 = int64_t(blockIdx.x) * (kBlock * kPerThread) + threadIdx.x;
+  const int64_t t0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * EPL;
+  if (t0 >= len) return;
+  double vr[EPL], vi[EPL];
 #pragma unroll
-  for (int e = 0; e < kPerThread; e++) {
-    const int64_t t = t0 + e * kBlock;
-    if (t >= len) break;
-    const uint64_t i = uint64_t(t + row0);
-    const uint64_t j = uint64_t(int64_t(i) + d);
-    double vr = 0, vi = 0;
-    if (((i ^ j) & ~a.tmask) == 0) {
-      if ((i & a.cmask) != a.cmask) {
-        vr = (i == j) ? 1.0 : 0.0;
-      } else {
-        int r = 0, c = 0;
-        for (int b = 0; b < a.k; b++) {
-          r |= int((i >> a.targets[b]) & 1) << b;
-          c |= int((j >> a.targets[b]) & 1) << b;
-        }
-        vr = sm[r * dim + c][0];
-        vi = sm[r * dim + c][1];
-      }
+  for (int e = 0; e < EPL; e++)
+    if (t0 + e < len) expanded_element(a, sm, dim, d, row0, t0 + e, vr[e], vi[e]);
+  if constexpr (EPL == 2) {
+    if (t0 + 1 < len && ((a.start[kd] + t0) & 1) == 0) {
+      const float4 w{float(vr[0]), float(vi[0]), float(vr[1]), float(vi[1])};
+      *reinterpret_cast<float4*>(dst + t0) = w;
+      return;
     }
-    // folded diagonal gates D after the core: (D A)[i, j] = D(i) A[i, j]
-    for (int f = 0; f < a.nf; f++) {
-      const DiagFactor& fa = a.factors[f];
-      int r = 0;
-      for (int b = 0; b < fa.k; b++) r |= int((i >> fa.q[b]) & 1) << b;
-      const double fr = fa.v[r][0], fi = fa.v[r][1];
-      const double nr = vr * fr - vi * fi;
-      vi = vr * fi + vi * fr;
-      vr = nr;
-    }
-    put<NT>(dst + t, V{R(vr), R(vi)});
   }
+#pragma unroll
+  for (int e = 0; e < EPL; e++)
+    if (t0 + e < len) put<NT>(dst + t0 + e, V{R(vr[e]), R(vi[e])});
 }
 
 // Pauli-sum diagonals: element (i, j) = sum over terms with x == i ^ j of
@@ -171,7 +191,8 @@ diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n, diaq_dtyp
     maxlen = std::max<int64_t>(maxlen, a.N - (offs[q] < 0 ? -offs[q] : offs[q]));
   }
   std::memcpy(a.m, lg.m, sizeof(a.m));
-  const int64_t gx = (maxlen + kBlock * kPerThread - 1) / (kBlock * kPerThread);
+  const int64_t per_block = int64_t(kBlock) * (dt == DIAQ_C64 ? 2 : 1);
+  const int64_t gx = (maxlen + per_block - 1) / per_block;
   dim3 grid(unsigned(gx), unsigned(offs.size()));
   const bool nt = ctx->tuning.expand_nontemporal > 0;
   if (dt == DIAQ_C128) {
