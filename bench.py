@@ -218,9 +218,11 @@ def main():
     torch.cuda.synchronize()
     D.profile_start(ctx)
     t0 = time.perf_counter()
-    energies = []
+    energies, step_ms = [], []
     for _ in range(a.steps):
-        energies.append(step())
+        ts = time.perf_counter()
+        energies.append(step())  # reads the energy back: the step ends synchronised
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = D.profile_stop(ctx)
@@ -251,6 +253,8 @@ def main():
                                "<Z_iZ_i+1> energy" % (n, a.layers, len(gates), a.seed),
                    "n": n, "gates": len(gates), "layers": a.layers},
         "gates_per_s": round(len(gates) * a.steps / dt, 2),
+        "step_ms": {"mean": round(float(np.mean(step_ms)), 3), "std": round(float(np.std(step_ms)), 3),
+                    "median": round(float(np.median(step_ms)), 3), "steps": len(step_ms)},
         "tuning": tuning,
         "spmv_GBps": round(achieved, 1),
         "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)
@@ -278,6 +282,9 @@ def main():
         if a.dtype == "c128":
             out["c64"] = c64_extra(D, W, torch, gates, a.steps)
         out["tfim"] = tfim_extra(D, W, torch, ctx, state, scratch, tdt)
+        out["ghz12"] = ghz_extra(D, W, torch)
+        if a.dtype == "c128":
+            out["qft"] = qft_extra(D, W, torch, ctx)
         out["matrix"] = matrix_extra(D, W)
         out["adjoint"] = adjoint_extra(D, W, torch, dev)
         out["batch"] = batch_extra(D, W, torch, dev)
@@ -379,6 +386,85 @@ def tfim_extra(D, W, torch, ctx, state, scratch, tdt):
     out["magnetization"] = mags[0]
     out["max_magnetization_diff"] = max(abs(m - mags[0]) for m in mags)
     return out
+
+
+def ghz_extra(D, W, torch, reps=200):
+    """GHZ-12 (H then 11 CX from |0..0>, a 64 KiB state): microseconds per
+    gate when the host plans and launches every call, against the same
+    launches replayed from a recorded circuit graph."""
+    n = 12
+    gates = W.ghz(n)
+    arr = D.gate_array(gates)
+    psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda:0")
+    scratch = torch.empty_like(psi)
+    out = {"workload": "GHZ-12 from |0..0>, %d gates" % len(gates), "plans": []}
+    for name, plan in (("dia", None), ("kron", D.make_plan(kron=True)),
+                       ("kron+fuse3", D.make_plan(kron=True, fuse=True, max_fused_qubits=3))):
+        def reset():
+            psi.zero_()
+            psi[0] = 1
+
+        reset()
+        D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan, marshalled=arr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan, marshalled=arr)
+        torch.cuda.synchronize()
+        eager = (time.perf_counter() - t0) / reps
+        g = D.CircuitGraph(gates, psi, scratch=scratch, n=n, plan=plan)
+        g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.launch()
+        torch.cuda.synchronize()
+        graph = (time.perf_counter() - t0) / reps
+        reset()
+        g.launch()
+        host = psi.cpu().numpy()
+        err = max(abs(host[0] - 2 ** -0.5), abs(host[-1] - 2 ** -0.5), float(abs(host[1:-1]).max()))
+        out["plans"].append({"plan": name, "graph_nodes": g.nodes(), "eager_us_per_gate": round(eager / len(gates) * 1e6, 2),
+                             "graph_us_per_gate": round(graph / len(gates) * 1e6, 2),
+                             "max_err_vs_closed_form": err})
+        g.close()
+    return out
+
+
+def qft_extra(D, W, torch, ctx):
+    """QFT-24 and QFT-29 (textbook order: H and controlled-phase ladder per
+    qubit, then the reversing swaps) on a random state: logical gates/s and
+    the algorithmic rate of each plan, one timed run after a sizing run."""
+    rows = []
+    for n, seed in ((24, 24), (29, 29)):
+        gates = W.qft(n)
+        arr = D.gate_array(gates)
+        psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda:0")
+        scratch = torch.empty_like(psi)
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(seed)
+        for kw in ({}, {"fuse": True, "max_fused_qubits": 2}, {"kron": True},
+                   {"kron": True, "fuse": True, "max_fused_qubits": 3},
+                   {"kron": True, "fuse": True, "max_fused_qubits": 5}):
+            plan = D.make_plan(**kw) if kw else None
+            nops, nbytes = D.plan_count(gates, n, plan)
+            for _ in range(2):
+                psi.copy_(torch.randn(1 << n, dtype=torch.complex128, device="cuda:0", generator=g))
+                psi /= torch.linalg.vector_norm(psi)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            rows.append({"qft": n, "gates": len(gates),
+                         "plan": ("kron" if kw.get("kron") else "dia")
+                         + ("+fuse%d" % kw["max_fused_qubits"] if kw.get("fuse") else ""),
+                         "ops": nops, "ms": round(dt * 1e3, 2), "gates_per_s": round(len(gates) / dt, 1),
+                         "GBps": round(nbytes / dt / 1e9, 1),
+                         "norm": round(float(torch.linalg.vector_norm(psi).item()), 12)})
+        del psi, scratch
+        torch.cuda.empty_cache()
+    return rows
 
 
 def matrix_extra(D, W):

@@ -261,6 +261,31 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                  void* state, void* scratch,
                                  const diaq_plan_t* plan);
 
+/* Circuit graphs.  The launch sequence of one diaq_apply_circuit call over
+ * all of `gates` (same plan, same state and scratch pointers, the gate
+ * parameters as given now) recorded once into a HIP graph, then replayed
+ * with one launch per call: for short circuits on small states, where the
+ * host's planning and per-kernel launch cost exceed the kernels' run time.
+ * The graph owns its expansion and table workspaces (other calls on the
+ * context never touch them) and re-uploads its small tables from pinned
+ * host memory on every replay, so replays are independent of whatever ran
+ * in between.  Creating the graph runs nothing; each launch applies the
+ * circuit once to `state` on the context's stream, like
+ * diaq_apply_circuit.  state and scratch must stay allocated while the
+ * graph lives.  Errors: INVALID_ARGUMENT as diaq_apply_circuit, or a graph
+ * of another device; OUT_OF_MEMORY; DEVICE if recording fails. */
+typedef struct diaq_graph* diaq_graph_t;
+diaq_status_t diaq_circuit_graph_create(diaq_ctx_t ctx, const diaq_gate_t* gates,
+                                        int64_t ngates, int32_t nqubits,
+                                        diaq_dtype_t dtype, void* state,
+                                        void* scratch, const diaq_plan_t* plan,
+                                        diaq_graph_t* out);
+diaq_status_t diaq_circuit_graph_launch(diaq_ctx_t ctx, diaq_graph_t graph);
+/* Number of nodes (kernels and copies) in the recorded graph. */
+diaq_status_t diaq_circuit_graph_nodes(diaq_graph_t graph, int64_t* nodes);
+/* Waits for the device, then releases the graph and its workspaces. */
+diaq_status_t diaq_circuit_graph_free(diaq_graph_t graph);
+
 /* Host-only: the number of expansion + product launches (operations)
  * diaq_apply_circuit issues for `gates` under `plan`, and the algorithmic
  * bytes they move (expansion writes plus product reads and writes, the

@@ -25,6 +25,16 @@ diaq_status_t fail(diaq_status_t st, const char* fmt, ...) {
 void clear_error() { g_err[0] = 0; }
 
 diaq_status_t ensure(diaq_ctx* ctx, Workspace* w, size_t bytes) {
+  if (ctx->capture) {
+    // nothing may be allocated or freed while a graph is being recorded
+    if (ctx->capture->sizing) {
+      w->want = std::max(w->want, bytes);
+      return DIAQ_OK;
+    }
+    if (w->bytes < bytes)
+      return fail(DIAQ_ERR_DEVICE, "graph workspace of %zu bytes, %zu needed", w->bytes, bytes);
+    return DIAQ_OK;
+  }
   if (w->bytes >= bytes) return DIAQ_OK;
   if (w->ptr) {
     // work queued on the stream may still use the old buffer
@@ -41,6 +51,28 @@ diaq_status_t ensure(diaq_ctx* ctx, Workspace* w, size_t bytes) {
     return fail(DIAQ_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes) failed: %s", want, hipGetErrorString(e));
   }
   w->bytes = want;
+  return DIAQ_OK;
+}
+
+diaq_status_t upload(diaq_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return DIAQ_OK;
+  if (Capture* c = ctx->capture) {
+    const size_t span = (bytes + 255) & ~size_t(255);
+    if (c->sizing) {
+      c->host_used += span;
+      return DIAQ_OK;
+    }
+    if (c->host_used + span > c->host_bytes)
+      return fail(DIAQ_ERR_DEVICE, "graph staging of %zu bytes overrun", c->host_bytes);
+    char* h = c->host + c->host_used;
+    std::memcpy(h, src, bytes);
+    c->host_used += span;
+    DIAQ_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, ctx->stream));
+    return DIAQ_OK;
+  }
+  // earlier work on the stream may still read the previous contents
+  DIAQ_HIP(hipStreamSynchronize(ctx->stream));
+  DIAQ_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
   return DIAQ_OK;
 }
 

@@ -127,9 +127,7 @@ diaq_status_t run_fused(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, d
   if (!table.empty()) {
     DIAQ_TRY(ensure(ctx, &ctx->aux, table.size() * sizeof(DiagFactor)));
     dtab = static_cast<DiagFactor*>(ctx->aux.ptr);
-    // synchronous: the host table dies with this call
-    DIAQ_HIP(hipStreamSynchronize(ctx->stream));
-    DIAQ_HIP(hipMemcpy(dtab, table.data(), table.size() * sizeof(DiagFactor), hipMemcpyHostToDevice));
+    DIAQ_TRY(upload(ctx, dtab, table.data(), table.size() * sizeof(DiagFactor)));
   }
   void* x = state;
   void* y = scratch;
@@ -155,10 +153,7 @@ diaq_status_t upload_factors(diaq_ctx* ctx, const std::vector<FusedOp>& ops, Dia
   if (table.empty()) return DIAQ_OK;
   DIAQ_TRY(ensure(ctx, &ctx->aux, table.size() * sizeof(DiagFactor)));
   *dtab = static_cast<DiagFactor*>(ctx->aux.ptr);
-  // synchronous: the host table dies with this call
-  DIAQ_HIP(hipStreamSynchronize(ctx->stream));
-  DIAQ_HIP(hipMemcpy(*dtab, table.data(), table.size() * sizeof(DiagFactor), hipMemcpyHostToDevice));
-  return DIAQ_OK;
+  return upload(ctx, *dtab, table.data(), table.size() * sizeof(DiagFactor));
 }
 
 // Alg. 3 forward pass: every op applied in place on `state`, no expansion.
@@ -184,6 +179,48 @@ std::vector<FusedOp> unfused_ops(const Prepared& p) {
   return ops;
 }
 
+// gates[begin, end) applied to `state` on ctx->stream; arguments checked.
+diaq_status_t apply_range(diaq_ctx* ctx, const diaq_gate_t* gates, int64_t begin, int64_t end, int nqubits,
+                          diaq_dtype_t dtype, void* state, void* scratch, const diaq_plan_t* plan) {
+  const int saved_rows = ctx->spmv_rows;
+  if (plan && plan->rows_per_thread) ctx->spmv_rows = plan->rows_per_thread;
+  void* res = nullptr;
+  diaq_status_t st;
+  const int kmax = plan && plan->max_fused_qubits ? plan->max_fused_qubits : 2;
+  if (plan && plan->kron && plan->fuse && kmax > 3) {
+    // groups of four or five qubits: dense local matrices
+    std::vector<BigOp> ops;
+    st = plan_big(gates + begin, end - begin, nqubits, kmax, &ops);
+    if (st == DIAQ_OK) st = run_big(ctx, ops, nqubits, dtype, state);
+    res = state;
+  } else if (plan && plan->kron) {
+    std::vector<FusedOp> ops;
+    if (plan->fuse) {
+      st = plan_fusion(gates + begin, end - begin, nqubits, kmax, dtype, &ops, true);
+    } else {
+      Prepared p;
+      st = prepare_gates(gates + begin, end - begin, nqubits, &p);
+      if (st == DIAQ_OK) ops = unfused_ops(p);
+    }
+    if (st == DIAQ_OK) st = run_kron(ctx, ops, nqubits, dtype, state);
+    res = state;
+  } else if (plan && plan->fuse) {
+    std::vector<FusedOp> ops;
+    st = plan_fusion(gates + begin, end - begin, nqubits, kmax, dtype, &ops);
+    if (st == DIAQ_OK) st = run_fused(ctx, ops, nqubits, dtype, state, scratch, &res);
+  } else {
+    Prepared p;
+    st = prepare_gates(gates + begin, end - begin, nqubits, &p);
+    if (st == DIAQ_OK) st = run_plain(ctx, p, 0, end - begin, nqubits, dtype, state, scratch, &res);
+  }
+  ctx->spmv_rows = saved_rows;
+  DIAQ_TRY(st);
+  if (res != state)
+    DIAQ_HIP(hipMemcpyAsync(state, res, (size_t(1) << nqubits) * elem_bytes(dtype), hipMemcpyDeviceToDevice,
+                            ctx->stream));
+  return DIAQ_OK;
+}
+
 }  // namespace diaq
 
 using namespace diaq;
@@ -200,43 +237,7 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "gate range [%lld, %lld) outside [0, %lld]", (long long)begin,
                   (long long)end, (long long)ngates);
     DIAQ_TRY(check_vectors(nqubits, dtype, state, scratch));
-    const int saved_rows = ctx->spmv_rows;
-    if (plan && plan->rows_per_thread) ctx->spmv_rows = plan->rows_per_thread;
-    void* res = nullptr;
-    diaq_status_t st;
-    const int kmax = plan && plan->max_fused_qubits ? plan->max_fused_qubits : 2;
-    if (plan && plan->kron && plan->fuse && kmax > 3) {
-      // groups of four or five qubits: dense local matrices
-      std::vector<BigOp> ops;
-      st = plan_big(gates + begin, end - begin, nqubits, kmax, &ops);
-      if (st == DIAQ_OK) st = run_big(ctx, ops, nqubits, dtype, state);
-      res = state;
-    } else if (plan && plan->kron) {
-      std::vector<FusedOp> ops;
-      if (plan->fuse) {
-        st = plan_fusion(gates + begin, end - begin, nqubits, kmax, dtype, &ops, true);
-      } else {
-        Prepared p;
-        st = prepare_gates(gates + begin, end - begin, nqubits, &p);
-        if (st == DIAQ_OK) ops = unfused_ops(p);
-      }
-      if (st == DIAQ_OK) st = run_kron(ctx, ops, nqubits, dtype, state);
-      res = state;
-    } else if (plan && plan->fuse) {
-      std::vector<FusedOp> ops;
-      st = plan_fusion(gates + begin, end - begin, nqubits, kmax, dtype, &ops);
-      if (st == DIAQ_OK) st = run_fused(ctx, ops, nqubits, dtype, state, scratch, &res);
-    } else {
-      Prepared p;
-      st = prepare_gates(gates + begin, end - begin, nqubits, &p);
-      if (st == DIAQ_OK) st = run_plain(ctx, p, 0, end - begin, nqubits, dtype, state, scratch, &res);
-    }
-    ctx->spmv_rows = saved_rows;
-    DIAQ_TRY(st);
-    if (res != state)
-      DIAQ_HIP(hipMemcpyAsync(state, res, (size_t(1) << nqubits) * elem_bytes(dtype), hipMemcpyDeviceToDevice,
-                              ctx->stream));
-    return DIAQ_OK;
+    return apply_range(ctx, gates, begin, end, nqubits, dtype, state, scratch, plan);
   } catch (const std::bad_alloc&) {
     return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
@@ -425,6 +426,185 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
   } catch (const std::bad_alloc&) {
     return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Circuit graphs: one application of a gate list recorded once and replayed
+// ---------------------------------------------------------------------------
+
+struct diaq_graph {
+  int device = 0;
+  diaq::Workspace diag, aux, red;  // owned: other calls never touch them
+  char* host = nullptr;            // pinned tables the replay copies in
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t nodes = 0;
+};
+
+namespace {
+
+void release_graph(diaq_graph* G) {
+  if (!G) return;
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->g) (void)hipGraphDestroy(G->g);
+  if (G->diag.ptr) (void)hipFree(G->diag.ptr);
+  if (G->aux.ptr) (void)hipFree(G->aux.ptr);
+  if (G->red.ptr) (void)hipFree(G->red.ptr);
+  if (G->host) (void)hipHostFree(G->host);
+  delete G;
+}
+
+diaq_status_t alloc_exact(Workspace* w) {
+  if (w->want == 0) return DIAQ_OK;
+  const hipError_t e = hipMalloc(&w->ptr, w->want);
+  if (e != hipSuccess) {
+    w->ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(DIAQ_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes) for a circuit graph: %s", w->want,
+                hipGetErrorString(e));
+  }
+  w->bytes = w->want;
+  return DIAQ_OK;
+}
+
+// Record apply_range on `cs` with the graph's workspaces swapped into the
+// context.  The context is restored whatever happens.
+diaq_status_t record(diaq_ctx* ctx, diaq_graph* G, Capture* cap, hipStream_t cs, const diaq_gate_t* gates,
+                     int64_t ngates, int nqubits, diaq_dtype_t dtype, void* state, void* scratch,
+                     const diaq_plan_t* plan, hipGraph_t* out) {
+  std::swap(ctx->diag, G->diag);
+  std::swap(ctx->aux, G->aux);
+  std::swap(ctx->red, G->red);
+  const hipStream_t saved_stream = ctx->stream;
+  const bool saved_prof = ctx->profiling;
+  ctx->stream = cs;
+  ctx->profiling = false;
+  ctx->capture = cap;
+  diaq_status_t st = DIAQ_OK;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    st = fail(DIAQ_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  } else {
+    st = apply_range(ctx, gates, 0, ngates, nqubits, dtype, state, scratch, plan);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (st == DIAQ_OK && e != hipSuccess)
+      st = fail(DIAQ_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (st == DIAQ_OK) {
+      *out = g;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  (void)hipGetLastError();
+  ctx->capture = nullptr;
+  ctx->profiling = saved_prof;
+  ctx->stream = saved_stream;
+  std::swap(ctx->diag, G->diag);
+  std::swap(ctx->aux, G->aux);
+  std::swap(ctx->red, G->red);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+diaq_status_t diaq_circuit_graph_create(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_t ngates, int32_t nqubits,
+                                        diaq_dtype_t dtype, void* state, void* scratch, const diaq_plan_t* plan,
+                                        diaq_graph_t* out) {
+  if (!out) return fail(DIAQ_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(DIAQ_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  if (ctx->capture) return fail(DIAQ_ERR_INVALID_ARGUMENT, "the context is already recording a graph");
+  if (ngates < 0 || (ngates > 0 && !gates)) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad gate list");
+  DIAQ_TRY(check_vectors(nqubits, dtype, state, scratch));
+  diaq_graph* G = nullptr;
+  hipStream_t cs = nullptr;
+  try {
+    G = new diaq_graph;
+    G->device = ctx->device;
+    // the legacy stream cannot be recorded: a private stream of default
+    // priority carries the recording
+    const hipError_t ce = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (ce != hipSuccess) {
+      (void)hipGetLastError();
+      release_graph(G);
+      return fail(DIAQ_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(ce));
+    }
+    Capture cap;
+    hipGraph_t g = nullptr;
+    diaq_status_t st = record(ctx, G, &cap, cs, gates, ngates, nqubits, dtype, state, scratch, plan, &g);
+    if (st == DIAQ_OK) {
+      (void)hipGraphDestroy(g);
+      g = nullptr;
+      st = alloc_exact(&G->diag);
+      if (st == DIAQ_OK) st = alloc_exact(&G->aux);
+      if (st == DIAQ_OK) st = alloc_exact(&G->red);
+      if (st == DIAQ_OK && cap.host_used) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&G->host), cap.host_used, hipHostMallocDefault) != hipSuccess) {
+          G->host = nullptr;
+          (void)hipGetLastError();
+          st = fail(DIAQ_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes", cap.host_used);
+        }
+      }
+    }
+    if (st == DIAQ_OK) {
+      cap.sizing = false;
+      cap.host = G->host;
+      cap.host_bytes = cap.host_used;
+      cap.host_used = 0;
+      st = record(ctx, G, &cap, cs, gates, ngates, nqubits, dtype, state, scratch, plan, &g);
+    }
+    if (st == DIAQ_OK) {
+      G->g = g;
+      size_t nn = 0;
+      if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess) G->nodes = int64_t(nn);
+      const hipError_t ie = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        G->exec = nullptr;
+        (void)hipGetLastError();
+        st = fail(DIAQ_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+      }
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != DIAQ_OK) {
+      release_graph(G);
+      return st;
+    }
+    *out = G;
+    return DIAQ_OK;
+  } catch (const std::bad_alloc&) {
+    if (cs) (void)hipStreamDestroy(cs);
+    release_graph(G);
+    return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+diaq_status_t diaq_circuit_graph_launch(diaq_ctx_t ctx, diaq_graph_t graph) {
+  if (!ctx || !graph) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL context or graph");
+  if (graph->device != ctx->device)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "graph of device %d launched from a context of device %d", graph->device,
+                ctx->device);
+  if (ctx->capture) return fail(DIAQ_ERR_INVALID_ARGUMENT, "the context is recording a graph");
+  DIAQ_HIP(hipGraphLaunch(graph->exec, ctx->stream));
+  return DIAQ_OK;
+}
+
+diaq_status_t diaq_circuit_graph_nodes(diaq_graph_t graph, int64_t* nodes) {
+  if (!graph || !nodes) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL graph or output");
+  *nodes = graph->nodes;
+  return DIAQ_OK;
+}
+
+diaq_status_t diaq_circuit_graph_free(diaq_graph_t graph) {
+  if (!graph) return DIAQ_OK;
+  // a replay still in flight reads the graph's workspaces
+  DIAQ_HIP(hipDeviceSynchronize());
+  release_graph(graph);
+  return DIAQ_OK;
 }
 
 }  // extern "C"

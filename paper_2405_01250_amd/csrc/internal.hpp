@@ -76,6 +76,19 @@ struct Nat<float> {
 struct Workspace {
   void* ptr = nullptr;
   size_t bytes = 0;
+  size_t want = 0;  // largest request seen while sizing a graph recording
+};
+
+// Recording of a circuit's launches into a HIP graph.  The first recording
+// (sizing) is discarded: it only collects the workspace sizes and the bytes
+// of host tables; the second runs against workspaces of exactly those sizes
+// and stages each table in pinned host memory that the graph copies from on
+// every replay.
+struct Capture {
+  bool sizing = true;
+  char* host = nullptr;
+  size_t host_bytes = 0;
+  size_t host_used = 0;
 };
 
 }  // namespace diaq
@@ -102,6 +115,8 @@ struct diaq_ctx {
     double bytes;
   };
   std::vector<Interval> intervals;
+  // set while a circuit graph is being recorded on `stream`
+  diaq::Capture* capture = nullptr;
 };
 
 struct diaq_dia {
@@ -366,6 +381,11 @@ diaq_status_t fuse_dia(diaq_ctx* ctx, const diaq_dia* first,
 
 // Workspace growth (never shrinks).
 diaq_status_t ensure(diaq_ctx* ctx, Workspace* w, size_t bytes);
+// Copy a host table that dies with the calling function into device memory
+// ahead of the launches that read it: synchronous (after the stream's
+// earlier work) when running eagerly, a copy node from pinned staging when
+// a graph is being recorded.
+diaq_status_t upload(diaq_ctx* ctx, void* dst, const void* src, size_t bytes);
 diaq_status_t ensure_pinned(diaq_ctx* ctx, size_t bytes);
 
 // Qubit mask of the off-diagonal structure implied by an offset list.

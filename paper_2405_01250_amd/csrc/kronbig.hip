@@ -302,12 +302,8 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
   const size_t bytes = mb + facs.size() * sizeof(DiagFactor) + 256;
   DIAQ_TRY(ensure(ctx, &ctx->aux, bytes));
   char* base = static_cast<char*>(ctx->aux.ptr);
-  // synchronous: the host tables die with this call, and earlier work on the
-  // stream may still read the previous contents of the workspace
-  DIAQ_HIP(hipStreamSynchronize(ctx->stream));
-  if (!mats.empty()) DIAQ_HIP(hipMemcpy(base, mats.data(), mats.size() * sizeof(double), hipMemcpyHostToDevice));
-  if (!facs.empty())
-    DIAQ_HIP(hipMemcpy(base + mb, facs.data(), facs.size() * sizeof(DiagFactor), hipMemcpyHostToDevice));
+  DIAQ_TRY(upload(ctx, base, mats.data(), mats.size() * sizeof(double)));
+  DIAQ_TRY(upload(ctx, base + mb, facs.data(), facs.size() * sizeof(DiagFactor)));
   const double* dm = reinterpret_cast<const double*>(base);
   const DiagFactor* df = reinterpret_cast<const DiagFactor*>(base + mb);
   const double bytes_op = 2.0 * double(elem_bytes(dt)) * double(N);

@@ -118,6 +118,11 @@ _SIGS = {
                      ctypes.POINTER(_P)],
     "diaq_density_evolve": [_P, ctypes.POINTER(diaq_gate_t), _I64, _P, _D, ctypes.POINTER(diaq_chain_step_t),
                             ctypes.POINTER(_P)],
+    "diaq_circuit_graph_create": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _P, _P,
+                                  ctypes.POINTER(diaq_plan_t), ctypes.POINTER(_P)],
+    "diaq_circuit_graph_launch": [_P, _P],
+    "diaq_circuit_graph_nodes": [_P, ctypes.POINTER(_I64)],
+    "diaq_circuit_graph_free": [_P],
     "diaq_profile_start": [_P],
     "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
@@ -452,6 +457,47 @@ def apply_circuit(gates: Sequence, state: torch.Tensor, n: int | None = None, sc
                                      _vec(scratch, n, dt, "scratch"),
                                      ctypes.byref(plan) if plan is not None else None))
     return state
+
+
+class CircuitGraph:
+    """One application of `gates` to `state` (with `scratch`) under `plan`,
+    recorded once as a HIP graph; ``launch()`` replays it on the context's
+    stream.  The graph keeps `state` and `scratch` alive."""
+
+    def __init__(self, gates: Sequence, state: torch.Tensor, scratch: torch.Tensor | None = None,
+                 n: int | None = None, plan: diaq_plan_t | None = None, ctx: Context | None = None):
+        self.ctx = ctx or context(state.device.index)
+        if n is None:
+            n = int(state.numel()).bit_length() - 1
+        dt = _dtype_code(state.dtype)
+        self.state = state
+        self.scratch = scratch if scratch is not None else torch.empty_like(state)
+        arr, keep = gate_array(gates)
+        h = _P()
+        _check(load().diaq_circuit_graph_create(self.ctx.handle, arr, len(gates), n, dt,
+                                                _vec(state, n, dt, "state"), _vec(self.scratch, n, dt, "scratch"),
+                                                ctypes.byref(plan) if plan is not None else None, ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self) -> torch.Tensor:
+        _check(load().diaq_circuit_graph_launch(self.ctx.handle, self.handle))
+        return self.state
+
+    def nodes(self) -> int:
+        v = _I64()
+        _check(load().diaq_circuit_graph_nodes(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().diaq_circuit_graph_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def expect(H: DiaqMatrix, psi: torch.Tensor, phi: torch.Tensor | None = None) -> complex:
