@@ -48,12 +48,12 @@ std::vector<int64_t> workspace_starts(const diaq_ctx* ctx, const std::vector<int
 }
 
 diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t>& offs, int n, diaq_dtype_t dt,
-                   bool adjoint, void** x, void** y, const DiagFactor* factors = nullptr, int nf = 0) {
+                   bool adjoint, void** x, void** y, const char* tabs = nullptr, int nt = 0) {
   const std::vector<int64_t> st = workspace_starts(ctx, offs, n);
   const double s = double(elem_bytes(dt));
   const double E = double(packing_starts(offs, n).back()), N = double(int64_t(1) << n);
   const size_t e0 = prof_mark(ctx);
-  DIAQ_TRY(launch_expand(ctx, lg, n, dt, offs, st, ctx->diag.ptr, factors, nf));
+  DIAQ_TRY(launch_expand(ctx, lg, n, dt, offs, st, ctx->diag.ptr, tabs, nt));
   const size_t e1 = prof_mark(ctx);
   prof_interval(ctx, e0, e1, 0, s * E);
   struct Close {
@@ -110,62 +110,49 @@ diaq_status_t run_plain(diaq_ctx* ctx, const Prepared& p, int64_t begin, int64_t
 diaq_status_t run_fused(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, diaq_dtype_t dt, void* state,
                         void* scratch, void** result) {
   std::vector<std::vector<int64_t>> offs(ops.size());
-  std::vector<DiagFactor> table;
-  std::vector<size_t> first(ops.size());
+  OpTables tabs;
   int64_t max_values = 0;
   for (size_t k = 0; k < ops.size(); k++) {
     offs[k] = gate_offsets(ops[k].core);
     if (offs[k].size() > size_t(kMaxArgDiags))
       return fail(DIAQ_ERR_UNSUPPORTED, "fused op %zu has %zu diagonals", k, offs[k].size());
     max_values = std::max<int64_t>(max_values, packing_starts(offs[k], n).back());
-    first[k] = table.size();
-    table.insert(table.end(), ops[k].post.begin(), ops[k].post.end());
+    tabs.add(ops[k].post);
   }
   const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
   DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(max_values + (kMaxArgDiags + 1) * pad) * elem_bytes(dt)));
-  DiagFactor* dtab = nullptr;
-  if (!table.empty()) {
-    DIAQ_TRY(ensure(ctx, &ctx->aux, table.size() * sizeof(DiagFactor)));
-    dtab = static_cast<DiagFactor*>(ctx->aux.ptr);
-    DIAQ_TRY(upload(ctx, dtab, table.data(), table.size() * sizeof(DiagFactor)));
+  const char* dtab = nullptr;
+  if (!tabs.bytes.empty()) {
+    DIAQ_TRY(ensure(ctx, &ctx->aux, tabs.bytes.size()));
+    dtab = static_cast<const char*>(ctx->aux.ptr);
+    DIAQ_TRY(upload(ctx, ctx->aux.ptr, tabs.bytes.data(), tabs.bytes.size()));
   }
   void* x = state;
   void* y = scratch;
   for (size_t k = 0; k < ops.size(); k++) {
-    const int nf = int(ops[k].post.size());
-    DIAQ_TRY(step(ctx, ops[k].core, offs[k], n, dt, false, &x, &y, nf ? dtab + first[k] : nullptr, nf));
+    const int nt = tabs.count[k];
+    DIAQ_TRY(step(ctx, ops[k].core, offs[k], n, dt, false, &x, &y, nt ? dtab + tabs.first[k] : nullptr, nt));
   }
   *result = x;
   return DIAQ_OK;
 }
 
-// Copy the ops' folded diagonal factors into one device table; first[k] is
-// op k's first entry.
-diaq_status_t upload_factors(diaq_ctx* ctx, const std::vector<FusedOp>& ops, DiagFactor** dtab,
-                             std::vector<size_t>* first) {
-  std::vector<DiagFactor> table;
-  first->resize(ops.size());
-  for (size_t k = 0; k < ops.size(); k++) {
-    (*first)[k] = table.size();
-    table.insert(table.end(), ops[k].post.begin(), ops[k].post.end());
-  }
-  *dtab = nullptr;
-  if (table.empty()) return DIAQ_OK;
-  DIAQ_TRY(ensure(ctx, &ctx->aux, table.size() * sizeof(DiagFactor)));
-  *dtab = static_cast<DiagFactor*>(ctx->aux.ptr);
-  return upload(ctx, *dtab, table.data(), table.size() * sizeof(DiagFactor));
-}
-
 // Alg. 3 forward pass: every op applied in place on `state`, no expansion.
 diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, diaq_dtype_t dt, void* state) {
-  DiagFactor* dtab = nullptr;
-  std::vector<size_t> first;
-  DIAQ_TRY(upload_factors(ctx, ops, &dtab, &first));
+  OpTables tabs;
+  for (const FusedOp& op : ops) tabs.add(op.post);
+  const char* dtab = nullptr;
+  if (!tabs.bytes.empty()) {
+    DIAQ_TRY(ensure(ctx, &ctx->aux, tabs.bytes.size()));
+    dtab = static_cast<const char*>(ctx->aux.ptr);
+    DIAQ_TRY(upload(ctx, ctx->aux.ptr, tabs.bytes.data(), tabs.bytes.size()));
+  }
   for (size_t k = 0; k < ops.size(); k++) {
-    const int nf = int(ops[k].post.size());
+    const int nt = tabs.count[k];
     const size_t e0 = prof_mark(ctx);
-    DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false, nf ? dtab + first[k] : nullptr, nf));
-    prof_interval(ctx, e0, prof_mark(ctx), 1, kron_op_bytes(ops[k].core, nf, n, dt));
+    DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false,
+                               nt ? dtab + tabs.first[k] : nullptr, nt));
+    prof_interval(ctx, e0, prof_mark(ctx), 1, kron_op_bytes(ops[k].core, int(ops[k].post.size()), n, dt));
   }
   return DIAQ_OK;
 }

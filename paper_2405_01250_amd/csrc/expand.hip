@@ -38,8 +38,8 @@ struct ExpandArgs {
   int64_t off[kMaxArgDiags];
   int64_t start[kMaxArgDiags];
   double m[8][8][2];
-  const DiagFactor* factors;  // diagonal gates applied after the core
-  int32_t nf;
+  const char* tabs;  // diagonal gates applied after the core (factor tables)
+  int32_t nt;
   int32_t pad2;
 };
 
@@ -76,15 +76,7 @@ __device__ __forceinline__ void expanded_element(const ExpandArgs& a, const doub
     }
   }
   // folded diagonal gates D after the core: (D A)[i, j] = D(i) A[i, j]
-  for (int f = 0; f < a.nf; f++) {
-    const DiagFactor& fa = a.factors[f];
-    int r = 0;
-    for (int b = 0; b < fa.k; b++) r |= int((i >> fa.q[b]) & 1) << b;
-    const double fr = fa.v[r][0], fi = fa.v[r][1];
-    const double nr = vr * fr - vi * fi;
-    vi = vr * fi + vi * fr;
-    vr = nr;
-  }
+  if (a.nt) apply_tables(a.tabs, a.nt, i, vr, vi);
 }
 
 // One lane per element for complex128 (16-byte stores); two consecutive
@@ -170,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void pauli_kernel(int64_t N, const int64_t*
 
 diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n, diaq_dtype_t dt,
                             const std::vector<int64_t>& offs, const std::vector<int64_t>& starts, void* values,
-                            const DiagFactor* factors, int nf) {
+                            const void* tabs, int ntabs) {
   if (offs.size() > size_t(kMaxArgDiags))
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "gate occupies %zu diagonals (> %d)", offs.size(), kMaxArgDiags);
   if (offs.empty()) return DIAQ_OK;
@@ -182,8 +174,8 @@ diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n, diaq_dtyp
   for (int j = 0; j < lg.k; j++) a.targets[j] = lg.targets[j];
   a.tmask = lg.tmask;
   a.cmask = lg.cmask;
-  a.factors = factors;
-  a.nf = factors ? nf : 0;
+  a.tabs = static_cast<const char*>(tabs);
+  a.nt = tabs ? ntabs : 0;
   int64_t maxlen = 0;
   for (size_t q = 0; q < offs.size(); q++) {
     a.off[q] = offs[q];

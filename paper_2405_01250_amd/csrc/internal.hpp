@@ -172,6 +172,61 @@ struct DiagFactor {
   double v[8][2];
 };
 
+// Device form of an operation's folded diagonal factors.  Diagonal matrices
+// commute, so the factors are grouped by qubits and each group's product is
+// tabulated once on the host: a table over at most kTableQubits qubits,
+// indexed by the element's bits on those qubits.  An element then pays one
+// lookup per table instead of one per factor.  Tables follow one another
+// in memory: a header, then 2^nq complex entries (16-byte aligned).
+constexpr int kTableQubits = 8;
+struct TableHead {
+  int32_t nq;       // qubits of the table
+  int32_t nruns;    // runs of consecutive qubits; none crosses bit 32
+  int32_t run[10];  // first qubit | length << 8 | first index bit << 16
+};
+static_assert(sizeof(TableHead) == 48, "table header is 48 bytes");
+inline size_t table_bytes(int nq) { return sizeof(TableHead) + (size_t(16) << nq); }
+// Appends the tables of f[0..nf) to *out (planner.cpp); returns how many.
+int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out);
+
+// (vr, vi) *= the product of the nt tables at `tabs` at element i.
+__device__ __forceinline__ void apply_tables(const char* tabs, int nt, uint64_t i, double& vr, double& vi) {
+  typedef __attribute__((address_space(1))) const char GChar;
+  typedef __attribute__((address_space(1))) const TableHead GHead;
+  typedef __attribute__((address_space(1))) const double GDouble;
+  const uint32_t lo = uint32_t(i), hi = uint32_t(i >> 32);
+  GChar* p = (GChar*)(tabs);
+  for (int t = 0; t < nt; t++) {
+    GHead* h = (GHead*)(p);
+    const int nq = h->nq, nr = h->nruns;
+    uint32_t idx = 0;
+    for (int r = 0; r < nr; r++) {
+      const uint32_t w = uint32_t(h->run[r]);
+      const uint32_t src = w & 63u, len = (w >> 8) & 15u, dst = (w >> 16) & 15u;
+      const uint32_t word = src < 32u ? lo : hi;
+      idx |= ((word >> (src & 31u)) & ((1u << len) - 1u)) << dst;
+    }
+    GDouble* e = (GDouble*)(p + sizeof(TableHead));
+    const double fr = e[2 * idx], fi = e[2 * idx + 1];
+    const double nr2 = vr * fr - vi * fi;
+    vi = vr * fi + vi * fr;
+    vr = nr2;
+    p += sizeof(TableHead) + (size_t(16) << nq);
+  }
+}
+
+// Device tables of several operations' factors in one buffer: op k's tables
+// start at byte first[k] and number count[k].
+struct OpTables {
+  std::vector<char> bytes;
+  std::vector<size_t> first;
+  std::vector<int> count;
+  void add(const std::vector<DiagFactor>& post) {
+    first.push_back(bytes.size());
+    count.push_back(post.empty() ? 0 : compile_factors(post.data(), int(post.size()), &bytes));
+  }
+};
+
 // One expansion + product: a core gate (targets, controls, local matrix)
 // followed by diagonal gates applied after it.
 struct FusedOp {
@@ -228,7 +283,7 @@ struct DiagArgs {
 diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n,
                             diaq_dtype_t dt, const std::vector<int64_t>& offs,
                             const std::vector<int64_t>& starts, void* values,
-                            const DiagFactor* factors = nullptr, int nf = 0);
+                            const void* tabs = nullptr, int nt = 0);
 diaq_status_t launch_pauli_dia(diaq_ctx* ctx, int n, diaq_dtype_t dt,
                                const std::vector<int64_t>& offs,
                                const std::vector<int64_t>& starts,
@@ -266,7 +321,7 @@ diaq_status_t launch_generator_dot(diaq_ctx* ctx, const LocalGate& gen, int n,
 // (device, 4 x 4 complex, at most 2 targets) replaces lg's matrix when the
 // matrix depends on angles that live on the device.
 diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
-                                void* v, bool adjoint, const DiagFactor* factors = nullptr, int nf = 0,
+                                void* v, bool adjoint, const void* tabs = nullptr, int nt = 0,
                                 const double* dmat = nullptr);
 // Reverse-sweep step: optional generator dot (one double2 partial per
 // workgroup into `partial`, kron_adjoint_blocks of them), then

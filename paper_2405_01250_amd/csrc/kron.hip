@@ -40,8 +40,8 @@ struct KronArgs {
   int32_t sorted[3];   // target qubits ascending (zero-bit insertion)
   uint64_t cmask;
   int32_t adjoint;
-  int32_t nf;
-  const DiagFactor* factors;
+  int32_t nt;          // folded diagonal factors: tables at tabs
+  const char* tabs;
   const double* dmat;  // device 4 x 4 local matrix (k <= 2), replaces m
   double m[8][8][2];
   double g[8][8][2];   // generator (adjoint step with a dot)
@@ -84,18 +84,6 @@ __device__ __forceinline__ void mat_vec(const KronArgs& a, const double (&xr)[1 
   }
 }
 
-__device__ __forceinline__ void apply_factors(const KronArgs& a, int64_t i, double& vr, double& vi) {
-  for (int f = 0; f < a.nf; f++) {
-    const DiagFactor& fa = a.factors[f];
-    int r = 0;
-    for (int b = 0; b < fa.k; b++) r |= int((i >> fa.q[b]) & 1) << b;
-    const double fr = fa.v[r][0], fi = fa.v[r][1];
-    const double nr = vr * fr - vi * fi;
-    vi = vr * fi + vi * fr;
-    vr = nr;
-  }
-}
-
 // In place: v <- (M or M^dagger) v on every coset whose controls are 1,
 // then the folded diagonal factors.
 template <typename R, int K, bool DM>
@@ -126,13 +114,13 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
     mat_vec<K, DM>(a, xr[u], xi[u], yr, yi);
 #pragma unroll
     for (int r = 0; r < d; r++) {
-      if (a.nf) apply_factors(a, base[u] + a.off[r], yr[r], yi[r]);
+      if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(base[u] + a.off[r]), yr[r], yi[r]);
       v[base[u] + a.off[r]] = V{R(yr[r]), R(yi[r])};
     }
   }
   // rows whose controls are 0 keep their amplitude, but folded factors
   // still multiply them
-  if (a.nf && a.cmask) {
+  if (a.nt && a.cmask) {
 #pragma unroll
     for (int u = 0; u < kCosetsPerLane; u++) {
       const int64_t cb = c0 + u * kBlock;
@@ -143,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
       for (int r = 0; r < d; r++) {
         V t = v[b + a.off[r]];
         double tr = double(t.x), ti = double(t.y);
-        apply_factors(a, b + a.off[r], tr, ti);
+        apply_tables(a.tabs, a.nt, uint64_t(b + a.off[r]), tr, ti);
         v[b + a.off[r]] = V{R(tr), R(ti)};
       }
     }
@@ -157,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
     const bool on = (uint64_t(i) & a.cmask) == a.cmask;
-    if (!on && a.nf == 0) continue;  // an unfolded controlled phase leaves these rows alone
+    if (!on && a.nt == 0) continue;  // an unfolded controlled phase leaves these rows alone
     V t = v[i];
     double tr = double(t.x), ti = double(t.y);
     if (on) {
@@ -169,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
       ti = mr * ti + mi * tr;
       tr = nr;
     }
-    if (a.nf) apply_factors(a, i, tr, ti);
+    if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(i), tr, ti);
     v[i] = V{R(tr), R(ti)};
   }
 }
@@ -245,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void kron_adjoint_kernel(KronArgs a, typena
   }
 }
 
-KronArgs make_args(const LocalGate& lg, int n, bool adjoint, const DiagFactor* factors, int nf) {
+KronArgs make_args(const LocalGate& lg, int n, bool adjoint, const void* tabs, int nt) {
   KronArgs a;
   std::memset(&a, 0, sizeof(a));
   a.k = lg.k;
@@ -261,8 +249,8 @@ KronArgs make_args(const LocalGate& lg, int n, bool adjoint, const DiagFactor* f
   for (int j = 0; j < lg.k; j++) a.sorted[j] = st[j];
   a.cmask = lg.cmask;
   a.adjoint = adjoint ? 1 : 0;
-  a.factors = factors;
-  a.nf = factors ? nf : 0;
+  a.tabs = static_cast<const char*>(tabs);
+  a.nt = tabs ? nt : 0;
   std::memcpy(a.m, lg.m, sizeof(a.m));
   return a;
 }
@@ -318,9 +306,9 @@ double kron_op_bytes(const LocalGate& core, int nf, int n, diaq_dtype_t dt) {
 }
 
 diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
-                                void* v, bool adjoint, const DiagFactor* factors, int nf, const double* dmat) {
+                                void* v, bool adjoint, const void* tabs, int nt, const double* dmat) {
   if (dmat && lg.k > 2) return fail(DIAQ_ERR_UNSUPPORTED, "device matrices cover at most 2 targets");
-  KronArgs a = make_args(lg, n, adjoint, factors, nf);
+  KronArgs a = make_args(lg, n, adjoint, tabs, nt);
   a.dmat = dmat;
   const int64_t N = int64_t(1) << n;
   const bool diag = is_diagonal_local(lg);

@@ -22,7 +22,6 @@ namespace {
 using Cd = std::complex<double>;
 constexpr int kBigBlock = 256;
 constexpr int kBigMaxFactors = 64;
-static_assert(sizeof(DiagFactor) % sizeof(double) == 0, "factors are staged in 8-byte words");
 
 // Matrix of gate lg on the group qubits S (bit j of a local index is S[j]):
 // P_ctrl (x) M + (1 - P_ctrl) (x) 1, identity on the group's other qubits.
@@ -128,13 +127,13 @@ bool make_factor(const LocalGate& lg, DiagFactor* f) {
 
 struct BigArgs {
   int64_t ncos;
-  int32_t nf;
+  int32_t nt;
   int32_t pad;
   int32_t sorted[5];
   int32_t pad2;
   int64_t off[32];  // global offset of local index r
   const double* mat;             // D x D, row-major, interleaved complex
-  const DiagFactor* factors;     // applied to the output rows
+  const char* tabs;              // factor tables applied to the output rows
 };
 
 template <typename R>
@@ -153,15 +152,7 @@ __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename
   using V = typename Vec<R>::V;
   constexpr int D = 1 << K;
   __shared__ double2 sm[D * D];
-  __shared__ DiagFactor sf[kBigMaxFactors];
   for (int t = threadIdx.x; t < D * D; t += kBigBlock) sm[t] = double2{a.mat[2 * t], a.mat[2 * t + 1]};
-  {
-    // the row factors, staged beside the matrix (8-byte words)
-    constexpr int W = int(sizeof(DiagFactor) / sizeof(double));
-    const double* src = reinterpret_cast<const double*>(a.factors);
-    double* dst = reinterpret_cast<double*>(sf);
-    for (int t = threadIdx.x; t < a.nf * W; t += kBigBlock) dst[t] = src[t];
-  }
   __syncthreads();
   const int64_t c = int64_t(blockIdx.x) * kBigBlock + threadIdx.x;
   if (c >= a.ncos) return;
@@ -193,15 +184,7 @@ __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename
     double yr = (pr[0] + pr[1]) + (pr[2] + pr[3]);
     double yi = (pi[0] + pi[1]) + (pi[2] + pi[3]);
     const int64_t i = base + a.off[r];
-    for (int f = 0; f < a.nf; f++) {
-      const DiagFactor& fa = sf[f];
-      int t = 0;
-      for (int b = 0; b < fa.k; b++) t |= int((i >> fa.q[b]) & 1) << b;
-      const double fr = fa.v[t][0], fi = fa.v[t][1];
-      const double nr = yr * fr - yi * fi;
-      yi = yr * fi + yi * fr;
-      yr = nr;
-    }
+    if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(i), yr, yi);
     v[i] = V{R(yr), R(yi)};
   }
 }
@@ -287,32 +270,30 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
   // one table: every operation's matrix (2 D^2 doubles), then the factors
   std::vector<double> mats;
   std::vector<size_t> moff(ops.size());
-  std::vector<DiagFactor> facs;
-  std::vector<size_t> foff(ops.size());
+  OpTables tabs;
   for (size_t k = 0; k < ops.size(); k++) {
     moff[k] = mats.size();
     for (const Cd& z : ops[k].m) {
       mats.push_back(z.real());
       mats.push_back(z.imag());
     }
-    foff[k] = facs.size();
-    facs.insert(facs.end(), ops[k].post.begin(), ops[k].post.end());
+    tabs.add(ops[k].post);
   }
   const size_t mb = ((mats.size() * sizeof(double) + 255) / 256) * 256;
-  const size_t bytes = mb + facs.size() * sizeof(DiagFactor) + 256;
+  const size_t bytes = mb + tabs.bytes.size() + 256;
   DIAQ_TRY(ensure(ctx, &ctx->aux, bytes));
   char* base = static_cast<char*>(ctx->aux.ptr);
   DIAQ_TRY(upload(ctx, base, mats.data(), mats.size() * sizeof(double)));
-  DIAQ_TRY(upload(ctx, base + mb, facs.data(), facs.size() * sizeof(DiagFactor)));
+  DIAQ_TRY(upload(ctx, base + mb, tabs.bytes.data(), tabs.bytes.size()));
   const double* dm = reinterpret_cast<const double*>(base);
-  const DiagFactor* df = reinterpret_cast<const DiagFactor*>(base + mb);
   const double bytes_op = 2.0 * double(elem_bytes(dt)) * double(N);
   for (size_t k = 0; k < ops.size(); k++) {
     const BigOp& op = ops[k];
-    const int nf = int(op.post.size());
+    const int nt = tabs.count[k];
+    const char* tk = nt ? base + mb + tabs.first[k] : nullptr;
     const size_t e0 = prof_mark(ctx);
     if (op.raw) {
-      DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, op.lg, n, dt, state, false, nf ? df + foff[k] : nullptr, nf));
+      DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, op.lg, n, dt, state, false, tk, nt));
     } else if (op.k <= 3) {
       // small groups: the three-qubit kernels, controls already in the matrix
       LocalGate lg;
@@ -330,12 +311,12 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
           lg.m[r][c][1] = z.imag();
           lg.structural[r][c] = z != Cd(0, 0);
         }
-      DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, lg, n, dt, state, false, nf ? df + foff[k] : nullptr, nf));
+      DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, lg, n, dt, state, false, tk, nt));
     } else {
       BigArgs a;
       std::memset(&a, 0, sizeof(a));
       a.ncos = N >> op.k;
-      a.nf = nf;
+      a.nt = nt;
       for (int j = 0; j < op.k; j++) a.sorted[j] = op.q[j];
       for (int r = 0; r < (1 << op.k); r++) {
         int64_t o = 0;
@@ -344,7 +325,7 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
         a.off[r] = o;
       }
       a.mat = dm + moff[k];
-      a.factors = nf ? df + foff[k] : nullptr;
+      a.tabs = tk;
       const dim3 grid(unsigned((a.ncos + kBigBlock - 1) / kBigBlock)), block(kBigBlock);
       if (dt == DIAQ_C128) {
         if (op.k == 4) hipLaunchKernelGGL((kron_big_kernel<double, 4>), grid, block, 0, ctx->stream, a,

@@ -152,6 +152,67 @@ bool diagonal_factor(const diaq_gate_t* g, const LocalGate& lg, DiagFactor* f) {
 
 }  // namespace
 
+int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out) {
+  // group: each factor joins the table it widens least, within kTableQubits
+  std::vector<uint64_t> gmask;
+  std::vector<std::vector<int>> members;
+  for (int j = 0; j < nf; j++) {
+    uint64_t m = 0;
+    for (int b = 0; b < f[j].k; b++) m |= uint64_t(1) << f[j].q[b];
+    int best = -1, best_add = 65;
+    for (size_t g = 0; g < gmask.size(); g++) {
+      const int u = __builtin_popcountll(gmask[g] | m);
+      if (u > kTableQubits) continue;
+      const int add = u - __builtin_popcountll(gmask[g]);
+      if (add < best_add) {
+        best = int(g);
+        best_add = add;
+      }
+    }
+    if (best < 0) {
+      gmask.push_back(0);
+      members.emplace_back();
+      best = int(gmask.size()) - 1;
+    }
+    gmask[best] |= m;
+    members[best].push_back(j);
+  }
+  for (size_t g = 0; g < gmask.size(); g++) {
+    int Q[64], nq = 0;
+    for (int q = 0; q < 64; q++)
+      if ((gmask[g] >> q) & 1) Q[nq++] = q;
+    TableHead h;
+    std::memset(&h, 0, sizeof(h));
+    h.nq = nq;
+    for (int i = 0; i < nq;) {
+      int e = i;
+      while (e + 1 < nq && Q[e + 1] == Q[e] + 1 && Q[e + 1] != 32) e++;
+      h.run[h.nruns++] = Q[i] | ((e - i + 1) << 8) | (i << 16);
+      i = e + 1;
+    }
+    const size_t at = out->size();
+    out->resize(at + table_bytes(nq));
+    std::memcpy(out->data() + at, &h, sizeof(h));
+    double* v = reinterpret_cast<double*>(out->data() + at + sizeof(h));
+    // position of each factor qubit inside the table index
+    for (int idx = 0; idx < (1 << nq); idx++) {
+      Cd z(1, 0);
+      for (int j : members[g]) {
+        int r = 0;
+        for (int b = 0; b < f[j].k; b++) {
+          int pos = 0;
+          while (Q[pos] != f[j].q[b]) pos++;
+          r |= ((idx >> pos) & 1) << b;
+        }
+        z *= Cd(f[j].v[r][0], f[j].v[r][1]);
+      }
+      v[2 * idx] = z.real();
+      v[2 * idx + 1] = z.imag();
+    }
+  }
+  return int(gmask.size());
+}
+
 diaq_status_t plan_fusion(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, diaq_dtype_t dt,
                           std::vector<FusedOp>* ops, bool kron) {
   if (kmax < 1 || kmax > 3) return fail(DIAQ_ERR_INVALID_ARGUMENT, "max_fused_qubits must be 1..3");
