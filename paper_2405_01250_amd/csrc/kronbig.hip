@@ -189,6 +189,206 @@ __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename
   }
 }
 
+// Groups that touch the lowest qubits.  With a target at bit 0..2 the lanes
+// of the per-coset kernel above read amplitudes 2^(q_min+1) or more elements
+// apart, so each load instruction touches up to 64 cache lines.  Here a
+// wave owns 64 consecutive cosets, whose union is a set of contiguous runs
+// of at least 64 amplitudes: the wave loads it coalesced into LDS, each lane
+// then applies the matrix to its coset out of LDS (in place), and the wave
+// stores the set back coalesced.
+//
+// Index space: P = the group's qubits plus the 6 lowest other qubits,
+// ascending; bit j of a staging index e stands for element bit P[j].  The
+// block index fills the element bits outside P.  Staging slot of e:
+// e ^ ((e >> swz) & smask), which spreads the lanes' coset rows over the
+// LDS banks (swz = staging bit of lane bit 0; no swizzle, smask = 0, when
+// that is bit 0 and the lanes already sit in consecutive slots).
+constexpr int kLdsLanes = 64;
+constexpr int kLdsCosetBits = 6;
+// A group of up to four qubits is staged when it has a qubit below 3; a
+// five-qubit group only when it holds qubit 0 (its 32 x 32 product is close
+// to the memory time, and the staged kernel, with fewer waves per CU,
+// overlaps the two less well: measured 1.9 ms per n = 28 operation on the
+// per-coset path against 3.3 ms staged for qubits 1-5, 2.9 against 2.8 for
+// qubits 0-4).
+constexpr int kLowQubit = 3;
+inline bool staged(const int* q, int k) { return k >= 1 && (k <= 4 ? q[0] < kLowQubit : q[0] == 0); }
+
+struct LdsArgs {
+  int32_t npos;
+  int32_t pos[11];      // P ascending
+  int32_t nruns;
+  int32_t run[11];      // staging bits -> element bits: first e bit | len << 8 | first element bit << 16
+  int32_t swz;
+  int32_t smask;
+  int32_t nt;
+  int32_t pad0;
+  int64_t lane_off[kLdsCosetBits];  // element offset of lane bit i
+  int32_t lane_e[kLdsCosetBits];    // staging bit of lane bit i
+  int32_t pad;
+  int32_t eoff[32];     // staging offset of local index r
+  int64_t roff[32];     // element offset of local index r
+  int64_t joff[32];     // element offset of staging index 64 j
+  const double* mat;
+  const char* tabs;
+};
+
+__device__ __forceinline__ int64_t staging_to_element(const LdsArgs& a, int e) {
+  int64_t off = 0;
+  for (int r = 0; r < a.nruns; r++) {
+    const uint32_t w = uint32_t(a.run[r]);
+    const uint32_t src = w & 31u, len = (w >> 8) & 31u, dst = (w >> 16) & 63u;
+    off |= int64_t((uint32_t(e) >> src) & ((1u << len) - 1u)) << dst;
+  }
+  return off;
+}
+
+__device__ __forceinline__ int slot(const LdsArgs& a, int e) { return e ^ ((e >> a.swz) & a.smask); }
+
+// PARTS waves per block: wave p computes rows [p D / PARTS, (p + 1) D /
+// PARTS) of every coset, so the block shares one staged matrix and a
+// five-qubit group keeps enough waves per CU to overlap its arithmetic with
+// the memory stream.
+template <typename R, int K, int PARTS>
+__global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, typename Vec<R>::V* __restrict__ v) {
+  using V = typename Vec<R>::V;
+  constexpr int D = 1 << K;
+  constexpr int E = kLdsLanes * D;
+  constexpr int T = kLdsLanes * PARTS;  // lanes per block
+  constexpr int L = D / PARTS;           // loads per lane, rows per lane
+  __shared__ double2 sm[D * D];
+  __shared__ double2 sx[E];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < D * D; t += T) sm[t] = double2{a.mat[2 * t], a.mat[2 * t + 1]};
+  int64_t base = blockIdx.x;
+  for (int j = 0; j < a.npos; j++) {
+    const int p = a.pos[j];
+    base = (base & ((int64_t(1) << p) - 1)) | ((base >> p) << (p + 1));
+  }
+  // coalesced load of the block's amplitudes (consecutive e are consecutive
+  // elements within each run of at least 64), all loads in flight before
+  // the first LDS write; e = tid + T j maps to the disjoint sum of the
+  // element offsets of tid and of T j
+  const int64_t tid_el = base + staging_to_element(a, tid);
+  {
+    V t[L];
+#pragma unroll
+    for (int j = 0; j < L; j++) t[j] = v[tid_el + a.joff[j * PARTS]];
+#pragma unroll
+    for (int j = 0; j < L; j++) sx[slot(a, tid + j * T)] = double2{double(t[j].x), double(t[j].y)};
+  }
+  __syncthreads();
+  const int lane = tid & (kLdsLanes - 1), part = tid / kLdsLanes;
+  int el = 0;
+  int64_t lo = 0;
+#pragma unroll
+  for (int i = 0; i < kLdsCosetBits; i++)
+    if ((lane >> i) & 1) {
+      el |= 1 << a.lane_e[i];
+      lo |= a.lane_off[i];
+    }
+  double xr[D], xi[D];
+#pragma unroll
+  for (int r = 0; r < D; r++) {
+    const double2 t = sx[slot(a, el + a.eoff[r])];
+    xr[r] = t.x;
+    xi[r] = t.y;
+  }
+  // the other waves still read this coset's inputs
+  if (PARTS > 1) __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < L; rr++) {
+    const int r = part * L + rr;
+    double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      const double2 m = sm[r * D + q];
+      pr[q & 3] = fma(m.x, xr[q], fma(-m.y, xi[q], pr[q & 3]));
+      pi[q & 3] = fma(m.x, xi[q], fma(m.y, xr[q], pi[q & 3]));
+    }
+    double yr = (pr[0] + pr[1]) + (pr[2] + pr[3]);
+    double yi = (pi[0] + pi[1]) + (pi[2] + pi[3]);
+    if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(base + lo + a.roff[r]), yr, yi);
+    sx[slot(a, el + a.eoff[r])] = double2{yr, yi};
+  }
+  __syncthreads();
+  {
+    double2 t[L];
+#pragma unroll
+    for (int j = 0; j < L; j++) t[j] = sx[slot(a, tid + j * T)];
+#pragma unroll
+    for (int j = 0; j < L; j++) v[tid_el + a.joff[j * PARTS]] = V{R(t[j].x), R(t[j].y)};
+  }
+}
+
+// Staging layout for the group S (ascending) on n qubits; false if the
+// state has fewer than 64 cosets.
+bool make_lds_args(const int* S, int k, int n, LdsArgs* a) {
+  if (n < k + kLdsCosetBits) return false;
+  std::memset(a, 0, sizeof(*a));
+  int P[11], np = 0, nl = 0;
+  int lane_bits[kLdsCosetBits];
+  for (int b = 0; b < n && np < k + kLdsCosetBits; b++) {
+    bool in_s = false;
+    for (int j = 0; j < k; j++) in_s = in_s || S[j] == b;
+    if (!in_s && nl == kLdsCosetBits) continue;
+    if (!in_s) lane_bits[nl++] = b;
+    P[np++] = b;
+  }
+  a->npos = np;
+  for (int j = 0; j < np; j++) a->pos[j] = P[j];
+  auto eidx = [&](int b) {
+    int j = 0;
+    while (P[j] != b) j++;
+    return j;
+  };
+  for (int i = 0; i < np;) {
+    int e = i;
+    while (e + 1 < np && P[e + 1] == P[e] + 1) e++;
+    a->run[a->nruns++] = i | ((e - i + 1) << 8) | (P[i] << 16);
+    i = e + 1;
+  }
+  for (int i = 0; i < kLdsCosetBits; i++) {
+    a->lane_e[i] = eidx(lane_bits[i]);
+    a->lane_off[i] = int64_t(1) << lane_bits[i];
+  }
+  a->swz = a->lane_e[0];
+  a->smask = a->swz ? 15 : 0;
+  for (int r = 0; r < (1 << k); r++) {
+    int eo = 0;
+    int64_t ro = 0;
+    for (int j = 0; j < k; j++)
+      if ((r >> j) & 1) {
+        eo |= 1 << eidx(S[j]);
+        ro |= int64_t(1) << S[j];
+      }
+    a->eoff[r] = eo;
+    a->roff[r] = ro;
+  }
+  for (int j = 0; j < (1 << k); j++) {
+    int64_t o = 0;
+    for (int b = 0; b < k; b++)
+      if ((j >> b) & 1) o |= int64_t(1) << P[kLdsCosetBits + b];
+    a->joff[j] = o;
+  }
+  return true;
+}
+
+template <typename R>
+void launch_lds(const LdsArgs& a, int k, int n, hipStream_t stream, void* state) {
+  using V = typename Vec<R>::V;
+  const dim3 grid(unsigned((int64_t(1) << n) >> (k + kLdsCosetBits)));
+  const dim3 one(kLdsLanes), four(kLdsLanes * 4);
+  V* v = static_cast<V*>(state);
+  switch (k) {
+    case 1: hipLaunchKernelGGL((kron_lds_kernel<R, 1, 1>), grid, one, 0, stream, a, v); break;
+    case 2: hipLaunchKernelGGL((kron_lds_kernel<R, 2, 1>), grid, one, 0, stream, a, v); break;
+    case 3: hipLaunchKernelGGL((kron_lds_kernel<R, 3, 1>), grid, one, 0, stream, a, v); break;
+    case 4: hipLaunchKernelGGL((kron_lds_kernel<R, 4, 1>), grid, one, 0, stream, a, v); break;
+    default: hipLaunchKernelGGL((kron_lds_kernel<R, 5, 4>), grid, four, 0, stream, a, v); break;
+  }
+}
+
 }  // namespace
 
 diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops) {
@@ -292,8 +492,16 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
     const int nt = tabs.count[k];
     const char* tk = nt ? base + mb + tabs.first[k] : nullptr;
     const size_t e0 = prof_mark(ctx);
+    LdsArgs la;
     if (op.raw) {
       DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, op.lg, n, dt, state, false, tk, nt));
+    } else if (staged(op.q, op.k) && make_lds_args(op.q, op.k, n, &la)) {
+      la.mat = dm + moff[k];
+      la.tabs = tk;
+      la.nt = nt;
+      if (dt == DIAQ_C128) launch_lds<double>(la, op.k, n, ctx->stream, state);
+      else launch_lds<float>(la, op.k, n, ctx->stream, state);
+      DIAQ_HIP(hipGetLastError());
     } else if (op.k <= 3) {
       // small groups: the three-qubit kernels, controls already in the matrix
       LocalGate lg;

@@ -150,3 +150,33 @@ def test_kron_big_groups_complex64():
     psi = to_dev(x, torch.complex64)
     D.apply_circuit(gates, psi, plan=D.make_plan(kron=True, fuse=True, max_fused_qubits=5))
     assert_state_close(to_host(psi), ref, TOL32, "kmax=5 c64", l2tol=1e-4)
+
+
+def _group_gates(S, n):
+    """One fused group on the qubits S (U3 on each, CX chain through S),
+    then two diagonal gates reaching outside S (folded as row factors when
+    the group is full)."""
+    gates = [W.u3(0.3, 0.2, 0.1, S[0])]
+    for j in range(len(S) - 1):
+        gates += [W.cx(S[j], S[j + 1]), W.u3(0.4 + j, 0.25 * j, 0.1 + j, S[j + 1])]
+    outside = [q for q in range(n) if q not in S]
+    gates += [W.cp(0.7, S[0], outside[-1]), W.Gate("RZ", (outside[0],), (), (1.1,))]
+    return gates
+
+
+@pytest.mark.parametrize("S", [(0,), (1,), (2,), (0, 1), (0, 5), (1, 2, 9), (0, 1, 2, 3), (2, 7, 8, 12),
+                               (0, 1, 2, 3, 4), (0, 3, 6, 9, 11), (2, 4, 5, 10, 13), (0, 1, 2, 3, 5)])
+def test_kron_staged_low_qubit_groups(S):
+    """Groups touching qubits 0..2 are staged through LDS (a wave loads its
+    64 cosets' amplitudes coalesced): at the smallest state that has 64
+    cosets, and above it."""
+    for n in sorted({max(max(S) + 2, len(S) + 6), 15}):
+        gates = _group_gates(list(S), n)
+        x = W.random_state(n, n + len(S))
+        for kmax in (4, 5):
+            psi = to_dev(x)
+            D.apply_circuit(gates, psi, plan=D.make_plan(kron=True, fuse=True, max_fused_qubits=kmax))
+            assert_state_close(to_host(psi), orc.apply_circuit(x, n, gates), TOL64, "S=%s n=%d kmax=%d" % (S, n, kmax))
+        psi32 = to_dev(x, torch.complex64)
+        D.apply_circuit(gates, psi32, plan=D.make_plan(kron=True, fuse=True, max_fused_qubits=5))
+        assert_state_close(to_host(psi32), orc.apply_circuit(x, n, gates), TOL32, "S=%s n=%d c64" % (S, n))
