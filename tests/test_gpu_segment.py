@@ -58,7 +58,7 @@ def _terms(rng, n, count=6):
             for _ in range(count)]
 
 
-@pytest.mark.parametrize("n,seed", [(3, 1), (4, 2), (5, 3), (7, 4), (9, 5), (12, 6)])
+@pytest.mark.parametrize("n,seed", [(3, 1), (4, 2), (5, 3), (7, 4), (9, 5), (12, 6), (16, 7), (17, 8)])
 def test_segmented_sweep_matches_plain_and_fd(n, seed):
     rng = np.random.default_rng(seed)
     nparams = 6
