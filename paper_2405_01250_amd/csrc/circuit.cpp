@@ -360,6 +360,14 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     double* dots = static_cast<double*>(ctx->aux.ptr);
     char* dtable = static_cast<char*>(ctx->aux.ptr) + dots_bytes;
     DIAQ_HIP(hipMemsetAsync(dots, 0, size_t(ngates + 1) * 2 * sizeof(double), ctx->stream));
+    if (segmented) {
+      // per-segment partial sums, reduced in one launch after the sweep; the
+      // reduce records point into this buffer, so it is sized here for the
+      // generator dot below too (which must not reallocate it)
+      const int64_t rows = std::max<int64_t>(segment_partial_entries(sp, nqubits), (int64_t(1) << nqubits) / 256 + 1);
+      DIAQ_TRY(ensure(ctx, &ctx->red, size_t(rows) * sizeof(double2)));
+      segment_table_reds(sp, nqubits, dtable, static_cast<const double2*>(ctx->red.ptr), table);
+    }
     if (!table.empty()) {
       // synchronous: the host image dies with this call
       DIAQ_HIP(hipStreamSynchronize(ctx->stream));
@@ -376,7 +384,6 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     DIAQ_TRY(launch_generator_dot(ctx, ident, nqubits, dtype, psi, lam, dots));
     // reverse sweep
     if (segmented) {
-      DIAQ_TRY(ensure(ctx, &ctx->red, size_t(segment_blocks(nqubits)) * kSegMaxDots * sizeof(double2)));
       DIAQ_TRY(run_segments(ctx, ctx->stream, sp, nqubits, dtype, psi, lam, dtable,
                             static_cast<double2*>(ctx->red.ptr), dots));
     } else if (kron) {

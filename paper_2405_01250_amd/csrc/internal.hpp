@@ -388,6 +388,14 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
 // host image with slots[j] = output slot (pairs of doubles) of dot j.
 size_t segment_table_bytes(const SegmentPlan& P);
 void segment_table_host(const SegmentPlan& P, std::vector<char>& host, const std::vector<int64_t>& slots);
+// The reverse sweep's partial sums: every segment has its own rows (this
+// many double2 entries in all), and the table's last region holds one
+// reduce record per segment with dots, filled in by segment_table_reds
+// once the device addresses of the table and of the partials are known.
+int64_t segment_partial_entries(const SegmentPlan& P, int n);
+size_t segment_reds_offset(const SegmentPlan& P);
+void segment_table_reds(const SegmentPlan& P, int n, const void* table_dev, const double2* partial,
+                        std::vector<char>& host);
 int64_t segment_blocks(int n);
 // Byte offset of the matrix pool inside the device table.
 size_t segment_pool_offset(const SegmentPlan& P);

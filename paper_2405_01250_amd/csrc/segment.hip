@@ -700,38 +700,79 @@ diaq_status_t plan_segments(const std::vector<LocalGate>& lg, const std::vector<
 
 diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan& P, int n, diaq_dtype_t dt,
                            void* psi, void* lam, void* table_mem, double2* partial, double* dots) {
-  // table_mem: device copy of [gates | pool | dot slots], laid out by segment_table_bytes
+  // table_mem: device copy of [gates | pool | dot slots | reduce records],
+  // laid out by segment_table_bytes; each segment's partial sums have their
+  // own rows of `partial` (segment_partial_entries), so all dot sums run in
+  // one launch after the sweep
   char* t = static_cast<char*>(table_mem);
   const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
   const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
   const SegGate* dg = reinterpret_cast<const SegGate*>(t);
   const double* dp = reinterpret_cast<const double*>(t + gb);
-  const int64_t* ds = reinterpret_cast<const int64_t*>(t + gb + pb);
-  const int64_t ncos = (int64_t(1) << n) >> 3;
-  const int64_t blocks = (ncos + kSegBlock - 1) / kSegBlock;
+  const int64_t blocks = segment_blocks(n);
+  int64_t row = 0, ndots = 0, nred = 0;
   for (const Segment& seg : P.segs) {
     const SegArgs a = make_seg_args(seg, n, dg, dp);
+    double2* part = partial + row;
     if (dt == DIAQ_C128) {
-      if (seg.three) launch_segment<double, true>(P.forward, blocks, stream, a, psi, lam, partial);
-      else launch_segment<double, false>(P.forward, blocks, stream, a, psi, lam, partial);
+      if (seg.three) launch_segment<double, true>(P.forward, blocks, stream, a, psi, lam, part);
+      else launch_segment<double, false>(P.forward, blocks, stream, a, psi, lam, part);
     } else {
-      if (seg.three) launch_segment<float, true>(P.forward, blocks, stream, a, psi, lam, partial);
-      else launch_segment<float, false>(P.forward, blocks, stream, a, psi, lam, partial);
+      if (seg.three) launch_segment<float, true>(P.forward, blocks, stream, a, psi, lam, part);
+      else launch_segment<float, false>(P.forward, blocks, stream, a, psi, lam, part);
     }
     DIAQ_HIP(hipGetLastError());
-    if (seg.ndots) {
-      hipLaunchKernelGGL(segment_reduce_kernel, dim3(unsigned(seg.ndots)), dim3(256), 0, stream, partial, blocks,
-                         seg.ndots, ds + seg.dot_slot0, dots);
-      DIAQ_HIP(hipGetLastError());
-    }
+    row += blocks * seg.ndots;
+    ndots += seg.ndots;
+    nred += seg.ndots ? 1 : 0;
+  }
+  if (ndots) {
+    const GroupRed* reds = reinterpret_cast<const GroupRed*>(t + segment_reds_offset(P));
+    hipLaunchKernelGGL(grouped_reduce_kernel, dim3(unsigned(ndots)), dim3(256), 0, stream, reds, int(nred), dots);
+    DIAQ_HIP(hipGetLastError());
   }
   return DIAQ_OK;
 }
 
-size_t segment_table_bytes(const SegmentPlan& P) {
+int64_t segment_partial_entries(const SegmentPlan& P, int n) {
+  int64_t e = 0;
+  for (const Segment& seg : P.segs) e += segment_blocks(n) * seg.ndots;
+  return std::max<int64_t>(e, 1);
+}
+
+size_t segment_reds_offset(const SegmentPlan& P) {
   const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
   const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
-  return gb + pb + P.dot_gate.size() * sizeof(int64_t) + 256;
+  return gb + pb + ((P.dot_gate.size() * sizeof(int64_t) + 255) / 256) * 256;
+}
+
+void segment_table_reds(const SegmentPlan& P, int n, const void* table_dev, const double2* partial,
+                        std::vector<char>& host) {
+  const char* t = static_cast<const char*>(table_dev);
+  const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
+  const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
+  const size_t ro = segment_reds_offset(P);
+  int64_t row = 0, red0 = 0;
+  size_t k = 0;
+  for (const Segment& seg : P.segs) {
+    if (seg.ndots) {
+      GroupRed r;
+      std::memset(&r, 0, sizeof(r));
+      r.partial = partial + row;
+      r.blocks = segment_blocks(n);
+      r.ndots = seg.ndots;
+      r.slot = reinterpret_cast<const int64_t*>(t + gb + pb) + seg.dot_slot0;
+      r.red0 = red0;
+      std::memcpy(host.data() + ro + k * sizeof(GroupRed), &r, sizeof(r));
+      k++;
+      red0 += seg.ndots;
+    }
+    row += segment_blocks(n) * seg.ndots;
+  }
+}
+
+size_t segment_table_bytes(const SegmentPlan& P) {
+  return segment_reds_offset(P) + P.segs.size() * sizeof(GroupRed) + 256;
 }
 
 void segment_table_host(const SegmentPlan& P, std::vector<char>& host, const std::vector<int64_t>& slots) {

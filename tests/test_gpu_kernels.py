@@ -218,6 +218,22 @@ def test_fuse_hh_identity_and_ghz10():
     assert np.max(np.abs(dense_from_dia(n, diags) - orc.dense_matrix(n, gates))) <= 1e-14
 
 
+def test_fuse_group_diagonal_counts():
+    """Alg. 1 on expanded gates: H and its controlled-phase ladder stay on
+    three diagonals; U3, U3 and CX on one pair of qubits span -3..3 (any
+    further pair sum cancels to exact zeros and is dropped)."""
+    n = 5
+    ladder = [W.h(4)] + [W.cp(math.pi / 2 ** m, 4 - m, 4) for m in range(1, 5)]
+    for gates, want in ((ladder, [-16, 0, 16]),
+                        ([W.u3(0.3, 0.4, 0.5, 0), W.u3(0.6, 0.7, 0.8, 1), W.cx(0, 1)], list(range(-3, 4)))):
+        U = D.from_gate(gates[0], n)
+        for g in gates[1:]:
+            U = D.fuse(U, D.from_gate(g, n))
+        live = [d for d, v in U.diagonals().items() if np.max(np.abs(v)) > 1e-14]
+        assert sorted(live) == want
+        assert np.max(np.abs(dense_from_dia(n, U.diagonals()) - orc.dense_matrix(n, gates))) <= 1e-14
+
+
 def test_fuse_not_multiplyable():
     A = D.from_gate(W.h(0), 4)
     B = D.from_gate(W.h(0), 5)

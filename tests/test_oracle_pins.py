@@ -329,6 +329,19 @@ def test_hh_is_identity(orc):
     assert np.allclose(vals[0], 1, rtol=0, atol=1e-15)
 
 
+def test_fused_group_diagonal_counts(orc):
+    """Sec. VI, gate fusion: H followed by its controlled-phase ladder keeps
+    the three diagonals of H (the phases are diagonal); two adjacent U3 and
+    a CX on the same pair of qubits span the offsets -3..3."""
+    n = 5
+    ladder = [W.h(4)] + [W.cp(math.pi / 2 ** m, 4 - m, 4) for m in range(1, 5)]
+    offs, _ = orc.dia_from_dense(orc.dense_matrix(n, ladder))
+    assert offs == [-16, 0, 16]
+    for cx in (W.cx(0, 1), W.cx(1, 0)):
+        offs, _ = orc.dia_from_dense(orc.dense_matrix(n, [W.u3(0.3, 0.4, 0.5, 0), W.u3(0.6, 0.7, 0.8, 1), cx]))
+        assert offs == [-3, -2, -1, 0, 1, 2, 3]
+
+
 # --------------------------------------------------------------------------
 # Matrix-level simulation: unitary chains and density matrices (Sec. II-A)
 # --------------------------------------------------------------------------
