@@ -411,13 +411,14 @@ diaq_status_t diaq_get_tuning(diaq_ctx_t ctx, diaq_tuning_t* t);
 diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype,
                             const char* cache_path, diaq_tuning_t* out);
 
-/* Choose a plan (fusion depth 1..3, expanded DiaQ products or, when
- * allow_kron != 0, Alg. 3 in-place products) for one circuit: candidates
- * are ranked by a byte model (diaq_plan_count, weighted by the measured
- * expansion and product rates) and skipped when their largest expanded
- * operation would not fit in free device memory; the best `measure`
- * candidates are then timed on the circuit's first gates (at most 64) on a
- * scratch vector, and the fastest per gate wins.  Synchronises the stream. */
+/* Choose a plan (fusion depth 1..3 on expanded DiaQ products or, when
+ * allow_kron != 0, also Alg. 3 in-place products with groups of 1..5
+ * qubits) for one circuit: candidates are ranked by a byte model
+ * (diaq_plan_count, weighted by nominal product rates) and skipped when
+ * their largest expanded operation would not fit in free device memory;
+ * the best `measure` candidates are then timed on the circuit's first
+ * quarter (at least 64 gates, all of a shorter circuit) on scratch
+ * vectors, and the fastest wins.  Synchronises the stream. */
 diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                  int64_t ngates, int32_t nqubits,
                                  diaq_dtype_t dtype, int32_t allow_kron,

@@ -376,8 +376,9 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       *out = fit[0].plan;
       return DIAQ_OK;
     }
-    // time the leaders on the circuit's first gates
-    const int64_t ng = std::min<int64_t>(ngates, 64);
+    // time the leaders on the circuit's first quarter (at least 64 gates):
+    // a shorter prefix cuts wide groups short and favours narrow ones
+    const int64_t ng = std::min<int64_t>(ngates, std::max<int64_t>(64, ngates / 4));
     void* st = nullptr;
     void* sc = nullptr;
     const size_t vb = size_t(N) * size_t(s);
