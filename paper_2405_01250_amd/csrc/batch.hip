@@ -371,28 +371,46 @@ __global__ __launch_bounds__(kObsBlock) void grouped_init_kernel(const WideVec* 
 }
 
 // lambda = H psi for the diagonal observable; one partial <psi|lambda> per
-// workgroup.
+// workgroup.  A lane's amplitudes are loaded first, then each term is read
+// once (scalar loads: the term tables are constant while the kernel runs)
+// and applied to all of them.
 __global__ __launch_bounds__(kObsBlock) void grouped_observable_kernel(const WideVec* __restrict__ list, int count) {
   using ND = Nat<double>::T;
+  typedef __attribute__((address_space(4))) const uint64_t CU64;
+  typedef __attribute__((address_space(4))) const double CDouble;
   const WideVec& w = list[find_item(list, count)];
   const int64_t blk = int64_t(blockIdx.x) - w.block0;
   const auto* __restrict__ psi = gptr(reinterpret_cast<const ND*>(w.psi));
   auto* __restrict__ lam = gptr(reinterpret_cast<ND*>(w.lam));
-  const auto* __restrict__ zm = gptr(w.zm);
-  const auto* __restrict__ coef = gptr(w.coef);
+  CU64* zm = (CU64*)(w.zm);
+  CDouble* coef = (CDouble*)(w.coef);
   const int64_t N = w.N;
   const int nt = w.nt;
-  double re = 0, im = 0;
+  const int64_t i0 = blk * kObsSpan + threadIdx.x;
+  ND p[kObsPerLane];
+  double h[kObsPerLane];
+#pragma unroll
   for (int e = 0; e < kObsPerLane; e++) {
-    const int64_t i = blk * kObsSpan + int64_t(e) * kObsBlock + threadIdx.x;
+    const int64_t i = i0 + int64_t(e) * kObsBlock;
+    p[e] = i < N ? psi[i] : ND{0, 0};
+    h[e] = 0;
+  }
+  for (int t = 0; t < nt; t++) {
+    const uint64_t z = zm[t];
+    const double c = coef[t];
+#pragma unroll
+    for (int e = 0; e < kObsPerLane; e++)
+      h[e] += (__popcll(uint64_t(i0 + int64_t(e) * kObsBlock) & z) & 1) ? -c : c;
+  }
+  double re = 0, im = 0;
+#pragma unroll
+  for (int e = 0; e < kObsPerLane; e++) {
+    const int64_t i = i0 + int64_t(e) * kObsBlock;
     if (i >= N) break;
-    double h = 0;
-    for (int t = 0; t < nt; t++) h += (__popcll(uint64_t(i) & zm[t]) & 1) ? -coef[t] : coef[t];
-    const ND p = psi[i];
-    const ND l{h * p.x, h * p.y};
+    const ND l{h[e] * p[e].x, h[e] * p[e].y};
     lam[i] = l;
-    re += p.x * l.x + p.y * l.y;
-    im += p.x * l.y - p.y * l.x;
+    re += p[e].x * l.x + p[e].y * l.y;
+    im += p[e].x * l.y - p[e].y * l.x;
   }
   for (int off = 32; off >= 1; off >>= 1) {
     re += __shfl_xor(re, off, 64);
