@@ -286,6 +286,13 @@ diaq_status_t diaq_circuit_graph_nodes(diaq_graph_t graph, int64_t* nodes);
 /* Waits for the device, then releases the graph and its workspaces. */
 diaq_status_t diaq_circuit_graph_free(diaq_graph_t graph);
 
+/* Device-to-device copy of `bytes` from src to dst (device pointers, both
+ * 16-byte aligned, bytes a multiple of 16, no overlap) by a streaming
+ * kernel on the context's stream: the drivers' own state copies, exported
+ * as the plain-copy reference of bandwidth measurements.  Errors:
+ * INVALID_ARGUMENT for NULL, misaligned or overlapping buffers. */
+diaq_status_t diaq_copy(diaq_ctx_t ctx, const void* src, void* dst, size_t bytes);
+
 /* Host-only: the number of expansion + product launches (operations)
  * diaq_apply_circuit issues for `gates` under `plan`, and the algorithmic
  * bytes they move (expansion writes plus product reads and writes, the

@@ -203,8 +203,7 @@ diaq_status_t apply_range(diaq_ctx* ctx, const diaq_gate_t* gates, int64_t begin
   ctx->spmv_rows = saved_rows;
   DIAQ_TRY(st);
   if (res != state)
-    DIAQ_HIP(hipMemcpyAsync(state, res, (size_t(1) << nqubits) * elem_bytes(dtype), hipMemcpyDeviceToDevice,
-                            ctx->stream));
+    DIAQ_TRY(launch_copy(ctx->stream, res, state, (size_t(1) << nqubits) * elem_bytes(dtype)));
   return DIAQ_OK;
 }
 
@@ -228,6 +227,11 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
   } catch (const std::bad_alloc&) {
     return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
+}
+
+diaq_status_t diaq_copy(diaq_ctx_t ctx, const void* src, void* dst, size_t bytes) {
+  if (!ctx || (bytes && (!src || !dst))) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+  return launch_copy(ctx->stream, src, dst, bytes);
 }
 
 diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates, int32_t nqubits, diaq_dtype_t dtype,
@@ -313,7 +317,7 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
     }
     const bool kron = plan && plan->kron;
     // forward: psi = U psi0 (Alg. 3 plan: fused in-place operations)
-    DIAQ_HIP(hipMemcpyAsync(psi, psi0, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    DIAQ_TRY(launch_copy(ctx->stream, psi0, psi, vb));
     if (kron) {
       const int kmax = plan->max_fused_qubits > 0 ? plan->max_fused_qubits : 4;
       if (kmax > 3) {

@@ -191,9 +191,11 @@ int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out);
 
 // (vr, vi) *= the product of the nt tables at `tabs` at element i.
 __device__ __forceinline__ void apply_tables(const char* tabs, int nt, uint64_t i, double& vr, double& vi) {
-  typedef __attribute__((address_space(1))) const char GChar;
-  typedef __attribute__((address_space(1))) const TableHead GHead;
-  typedef __attribute__((address_space(1))) const double GDouble;
+  // constant address space: the tables are not written while a kernel
+  // runs, so the uniform header reads become scalar loads
+  typedef __attribute__((address_space(4))) const char GChar;
+  typedef __attribute__((address_space(4))) const TableHead GHead;
+  typedef __attribute__((address_space(4))) const double GDouble;
   const uint32_t lo = uint32_t(i), hi = uint32_t(i >> 32);
   GChar* p = (GChar*)(tabs);
   for (int t = 0; t < nt; t++) {
@@ -444,6 +446,9 @@ diaq_status_t fuse_dia(diaq_ctx* ctx, const diaq_dia* first,
 
 // Workspace growth (never shrinks).
 diaq_status_t ensure(diaq_ctx* ctx, Workspace* w, size_t bytes);
+// Device-to-device copy by a streaming kernel (16-byte aligned, a multiple
+// of 16 bytes, no overlap).
+diaq_status_t launch_copy(hipStream_t stream, const void* src, void* dst, size_t bytes);
 // Copy a host table that dies with the calling function into device memory
 // ahead of the launches that read it: synchronous (after the stream's
 // earlier work) when running eagerly, a copy node from pinned staging when

@@ -123,6 +123,7 @@ _SIGS = {
     "diaq_circuit_graph_launch": [_P, _P],
     "diaq_circuit_graph_nodes": [_P, ctypes.POINTER(_I64)],
     "diaq_circuit_graph_free": [_P],
+    "diaq_copy": [_P, _P, _P, ctypes.c_size_t],
     "diaq_profile_start": [_P],
     "diaq_profile_stop": [_P, ctypes.POINTER(diaq_profile_t)],
 }
@@ -498,6 +499,17 @@ class CircuitGraph:
             self.close()
         except Exception:
             pass
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
+    """dst <- src on the device (same size, contiguous, 16-byte aligned)."""
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+        raise ValueError("copy needs equal sizes")
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("copy needs contiguous tensors")
+    ctx = ctx or context(src.device.index)
+    _check(load().diaq_copy(ctx.handle, _P(src.data_ptr()), _P(dst.data_ptr()), src.numel() * src.element_size()))
+    return dst
 
 
 def expect(H: DiaqMatrix, psi: torch.Tensor, phi: torch.Tensor | None = None) -> complex:

@@ -85,3 +85,25 @@ def test_empty_circuit_graph():
     torch.cuda.synchronize()
     assert np.array_equal(to_host(psi), x)
     g.close()
+
+
+def test_device_copy():
+    """diaq_copy: bitwise copy of 16-byte aligned buffers; misaligned,
+    ragged or overlapping buffers are rejected and leave dst untouched."""
+    x = to_dev(W.random_state(11, 6))
+    y = torch.zeros_like(x)
+    D.copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    empty = torch.zeros(0, dtype=torch.complex128, device="cuda:0")
+    D.copy(empty, empty.clone())
+    raw = torch.zeros(4096, dtype=torch.uint8, device="cuda:0")
+    dst = torch.ones(4096, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(D.DiaqError):
+        D.copy(raw[8:], dst[:-8])  # source 8 bytes off 16-byte alignment
+    with pytest.raises(D.DiaqError):
+        D.copy(raw[:24], dst[:24])  # not a multiple of 16 bytes
+    with pytest.raises(D.DiaqError):
+        D.copy(raw[:2048], raw[1024:3072])  # overlap
+    torch.cuda.synchronize()
+    assert bool(torch.all(dst == 1))
