@@ -34,8 +34,8 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor peak
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--seed", type=int, default=28)
@@ -103,30 +103,39 @@ def _traffic_from_profiles(kernel_src: str):
 
 def cpu_baseline(n, gates, budget_s, bytes_of_gate):
     """The CPU oracle, as it stands, on the first gates of the same circuit
-    until the time budget is spent."""
-    import numpy as np
-
+    until the time budget is spent: on every host core, then (a third of
+    the budget) on one."""
     from oracle import oracle as orc
     from paper_2405_01250_amd import inputs as W
 
     orc.build()
-    psi = W.zero_state(n)
-    done, nbytes = 0, 0.0
-    t0 = time.perf_counter()
-    for g in gates:
-        orc.apply_gate(psi, n, g)
-        done += 1
-        nbytes += bytes_of_gate(g)
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
+
+    def sample(budget):
+        psi = W.zero_state(n)
+        done, nbytes = 0, 0.0
+        t0 = time.perf_counter()
+        for g in gates:
+            orc.apply_gate(psi, n, g)
+            done += 1
+            nbytes += bytes_of_gate(g)
+            if time.perf_counter() - t0 >= budget:
+                break
+        return done, nbytes, time.perf_counter() - t0
+
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    del psi, np
+    orc.set_threads(cores)
+    cores = orc.get_threads()
+    done, nbytes, dt = sample(budget_s)
+    orc.set_threads(1)
+    d1, b1, t1 = sample(max(3.0, budget_s / 3))
+    orc.set_threads(cores)
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
             "gates_per_s": done / dt,
             "sample": "first %d of %d gates of the n=%d random layered circuit, complex128, in-place "
                       "bit-manipulation oracle (C, OpenMP); GB/s uses the same algorithmic byte model "
-                      "as value" % (done, len(gates), n)}
+                      "as value" % (done, len(gates), n),
+            "one_core": {"value": b1 / t1 / 1e9, "unit": "GB/s", "gates_per_s": d1 / t1,
+                         "sample": "first %d gates, same circuit, one thread" % d1}}
 
 
 def sweep_mode(a):
@@ -285,14 +294,15 @@ def main():
     if a.extras:
         p = D.autotune_plan(gates, n, dtype=tdt, allow_kron=True, measure=3, ctx=ctx)
         out["autotuned_plan"] = {"fuse": p.fuse, "max_fused_qubits": p.max_fused_qubits, "kron": p.kron}
-        out["variants"] = [fused_extra(D, gates, state, scratch, ctx, n, a.steps, **kw)
+        xs = min(a.steps, 3)  # timed runs of each extra
+        out["variants"] = [fused_extra(D, gates, state, scratch, ctx, n, xs, **kw)
                            for kw in ({"fuse": True, "max_fused_qubits": 2}, {"fuse": True, "max_fused_qubits": 3},
                                       {"kron": True}, {"kron": True, "fuse": True, "max_fused_qubits": 2},
                                       {"kron": True, "fuse": True, "max_fused_qubits": 3},
                                       {"kron": True, "fuse": True, "max_fused_qubits": 4},
                                       {"kron": True, "fuse": True, "max_fused_qubits": 5})]
         if a.dtype == "c128":
-            out["c64"] = c64_extra(D, W, torch, gates, a.steps)
+            out["c64"] = c64_extra(D, W, torch, gates, xs)
         out["tfim"] = tfim_extra(D, W, torch, ctx, state, scratch, tdt)
         out["ghz12"] = ghz_extra(D, W, torch)
         if a.dtype == "c128":

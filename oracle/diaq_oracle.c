@@ -15,6 +15,12 @@
 #include <stdint.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
+
+/* Thread count of the parallel loops below (the CPU baseline is timed on
+ * all host cores and on one); no effect on any result. */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* State evolution by amplitude-index bit manipulation                 */

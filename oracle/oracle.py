@@ -70,8 +70,21 @@ def _c():
         lib.orc_pauli_sum_apply.restype = None
         lib.orc_inner.argtypes = [i64, P, P, P]
         lib.orc_inner.restype = None
+        lib.orc_set_threads.argtypes = [ci]
+        lib.orc_set_threads.restype = None
+        lib.orc_get_threads.argtypes = []
+        lib.orc_get_threads.restype = ci
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the C oracle's parallel loops (results do not depend on it)."""
+    _c().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_c().orc_get_threads())
 
 
 def _ptr(a: np.ndarray):
