@@ -182,7 +182,7 @@ def sweep_mode(a):
 def main():
     a = _args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if a.mode == "copy":

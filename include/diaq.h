@@ -53,7 +53,7 @@ typedef enum diaq_status {
   DIAQ_ERR_NOT_MULTIPLYABLE = 2, /* dimension mismatch (Alg. 1 / Alg. 2 guard) */
   DIAQ_ERR_OUT_OF_MEMORY = 3,    /* device or host allocation failed */
   DIAQ_ERR_DEVICE = 4,           /* a HIP runtime call failed */
-  DIAQ_ERR_UNSUPPORTED = 5       /* valid request that this build does not do */
+  DIAQ_ERR_UNSUPPORTED = 5       /* valid request that the library does not support */
 } diaq_status_t;
 
 typedef enum diaq_dtype {

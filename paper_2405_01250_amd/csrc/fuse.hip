@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void multiply_diagonals_kernel(
     }
     const V cv = V{R(ar), R(ai)};
     out[od.start + t] = cv;
-    // judged on the stored (possibly rounded-to-float) value
+    // decided on the stored (possibly rounded-to-float) value
     const double sr = double(cv.x), si = double(cv.y);
     nz = (tol2 == 0.0) ? (sr != 0.0 || si != 0.0) : (sr * sr + si * si > tol2);
   }
