@@ -231,14 +231,6 @@ __global__ __launch_bounds__(kBlock) void diag_inplace_kernel(int64_t N, int32_t
   }
 }
 
-// Device copy, one 16-byte vector per lane (the state copies of the circuit
-// drivers; also the copy reference of the bandwidth measurements).
-__global__ __launch_bounds__(kBlock) void copy16_kernel(int64_t n16, const double2* __restrict__ src,
-                                                       double2* __restrict__ dst) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n16) dst[i] = src[i];
-}
-
 // ---------------------------------------------------------------------------
 // Reductions: per-workgroup partial sums in fixed order, then one pass.
 // ---------------------------------------------------------------------------
@@ -550,22 +542,6 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
 diaq_status_t launch_final_reduce(hipStream_t stream, const double2* partial, int64_t count, double* dres) {
   hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(1024), 0, stream, partial, count,
                      reinterpret_cast<double2*>(dres));
-  DIAQ_HIP(hipGetLastError());
-  return DIAQ_OK;
-}
-
-diaq_status_t launch_copy(hipStream_t stream, const void* src, void* dst, size_t bytes) {
-  if (bytes == 0) return DIAQ_OK;
-  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | bytes) & 15)
-    return fail(DIAQ_ERR_INVALID_ARGUMENT, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
-  const char* s = static_cast<const char*>(src);
-  char* d = static_cast<char*>(dst);
-  if (s < d + bytes && d < s + bytes) return fail(DIAQ_ERR_INVALID_ARGUMENT, "copy source and destination overlap");
-  const int64_t n16 = int64_t(bytes / 16);
-  const int64_t blocks = (n16 + kBlock - 1) / kBlock;
-  if (blocks > 0x7fffffffLL) return fail(DIAQ_ERR_UNSUPPORTED, "copy of %zu bytes", bytes);
-  hipLaunchKernelGGL(copy16_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, n16,
-                     static_cast<const double2*>(src), static_cast<double2*>(dst));
   DIAQ_HIP(hipGetLastError());
   return DIAQ_OK;
 }
