@@ -246,7 +246,9 @@ typedef struct diaq_plan {
                                (1..3, 0 = 2) */
   int32_t kron;             /* 1: Alg. 3 products, no expanded diagonals */
   int32_t rows_per_thread;  /* SpMV rows per lane (0 = tuned default) */
-  int32_t block;            /* SpMV workgroup size (0 = tuned default) */
+  int32_t block;            /* SpMV workgroup size: 0 or 256 (the kernels are
+                               built for 256-lane workgroups; any other
+                               value is INVALID_ARGUMENT) */
   int32_t reserved[3];
 } diaq_plan_t;
 

@@ -223,6 +223,8 @@ diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "gate range [%lld, %lld) outside [0, %lld]", (long long)begin,
                   (long long)end, (long long)ngates);
     DIAQ_TRY(check_vectors(nqubits, dtype, state, scratch));
+    if (plan && plan->block != 0 && plan->block != 256)
+      return fail(DIAQ_ERR_INVALID_ARGUMENT, "plan.block %d: the kernels use 256-lane workgroups", plan->block);
     return apply_range(ctx, gates, begin, end, nqubits, dtype, state, scratch, plan);
   } catch (const std::bad_alloc&) {
     return fail(DIAQ_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -519,6 +521,8 @@ diaq_status_t diaq_circuit_graph_create(diaq_ctx_t ctx, const diaq_gate_t* gates
   if (ctx->capture) return fail(DIAQ_ERR_INVALID_ARGUMENT, "the context is already recording a graph");
   if (ngates < 0 || (ngates > 0 && !gates)) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad gate list");
   DIAQ_TRY(check_vectors(nqubits, dtype, state, scratch));
+  if (plan && plan->block != 0 && plan->block != 256)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "plan.block %d: the kernels use 256-lane workgroups", plan->block);
   diaq_graph* G = nullptr;
   hipStream_t cs = nullptr;
   try {

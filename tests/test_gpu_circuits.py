@@ -98,7 +98,11 @@ def test_apply_circuit_errors_leave_state_untouched():
         D.apply_circuit([W.h(0), W.Gate("H", (7,))], x)
     with pytest.raises(D.DiaqError):
         D.apply_circuit([W.h(0)], x, scratch=x)
+    with pytest.raises(D.DiaqError):
+        D.apply_circuit([W.h(0)], x, plan=D.make_plan(block=128))  # workgroups are 256 lanes
     assert torch.equal(x, before)
+    D.apply_circuit([W.h(0), W.h(0)], x, plan=D.make_plan(block=256))
+    assert torch.allclose(x, before, rtol=0, atol=1e-15)
 
 
 def test_norm_preserved_every_gate_n20():
