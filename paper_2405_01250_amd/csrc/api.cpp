@@ -261,6 +261,8 @@ diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t) {
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "diag_pad must be in [-1, 2^24]");
   if (t->spmv_group_min_qubit < 0 || t->spmv_group_min_qubit > 63)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_group_min_qubit must be in [0, 63]");
+  if (t->spmv_xcd_runs != 0 && t->spmv_xcd_runs != -1)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_xcd_runs must be 0 or -1");
   ctx->tuning = *t;
   return DIAQ_OK;
 }

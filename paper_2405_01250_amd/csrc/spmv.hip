@@ -43,7 +43,22 @@ struct RowMap {
   int32_t tile_log2;  // log2(rows per tile)
   int32_t ng;         // number of group bits (0..3)
   int32_t gbit[3];    // ascending qubit indices, each >= tile_log2
+  int32_t run_log2;   // XCD runs of 2^run_log2 tiles (0: launch order)
 };
+
+// Tile of workgroup b.  The device hands consecutive workgroups to its 8
+// XCDs in turn, and each XCD has its own L2, so a tile whose partner rows
+// sit 1, 2 or 4 tiles away would fetch them through another XCD's cache.
+// With run_log2 = r each XCD takes runs of 2^r consecutive tiles (chunks of
+// 8 runs; the last partial chunk keeps launch order), and a tile meets its
+// partner less than 2^r tiles away in the same L2.
+__device__ __forceinline__ int64_t tile_of(int64_t b, const RowMap& m) {
+  if (m.run_log2 == 0) return b;
+  const int64_t w = int64_t(1) << m.run_log2, chunk = 8 * w;
+  if (b >= (int64_t(gridDim.x) / chunk) * chunk) return b;
+  const int64_t in = b % chunk;
+  return (b - in) + (in % 8) * w + in / 8;
+}
 
 // Insert a zero bit at each group position (ascending) into v.
 __device__ __forceinline__ int64_t insert_zero_bits(int64_t v, const RowMap& m) {
@@ -205,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(DiagArgs da, DiagSrc src, 
                                                       const typename Vec<R>::V* __restrict__ x,
                                                       typename Vec<R>::V* __restrict__ y) {
   using V = typename Vec<R>::V;
-  const int64_t base = insert_zero_bits(int64_t(blockIdx.x) << m.tile_log2, m);
+  const int64_t base = insert_zero_bits(tile_of(int64_t(blockIdx.x), m) << m.tile_log2, m);
   V acc[G * RPT];
   int64_t row[G * RPT];
   dia_rows<R, RPT, G, CHECK, KC, NT, DM>(da, src, m, vals, x, base, acc, row);
@@ -263,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void expect_kernel(DiagArgs da, DiagSrc src
                                                         const typename Vec<R>::V* __restrict__ phi,
                                                         double2* __restrict__ partial) {
   using V = typename Vec<R>::V;
-  const int64_t base = insert_zero_bits(int64_t(blockIdx.x) << m.tile_log2, m);
+  const int64_t base = insert_zero_bits(tile_of(int64_t(blockIdx.x), m) << m.tile_log2, m);
   V acc[G * RPT];
   int64_t row[G * RPT];
   dia_rows<R, RPT, G, CHECK, KC, NT, DM>(da, src, m, vals, phi, base, acc, row);
@@ -433,6 +448,26 @@ Plan plan_rows(const SpmvOp& op, const diaq_tuning_t& t, int rpt_override) {
   p.g = 1 << nb;
   p.check = false;
   p.blocks = p.map.N >> (tile_log2 + nb);
+  // XCD runs, for matrices whose every off-tile diagonal couples tiles 1, 2
+  // or 4 apart (a gate on qubit tile_log2 .. tile_log2 + 2): runs twice
+  // the largest such distance; any other distance keeps launch order,
+  // which already keeps distances that are multiples of 8 on one XCD
+  if (nb == 0 && op.nd <= kMaxArgDiags && t.spmv_xcd_runs >= 0) {
+    int64_t dmax = 0;
+    bool plain = true;
+    const int64_t tile = int64_t(1) << tile_log2;
+    for (int k = 0; k < op.nd; k++) {
+      const int64_t d = op.host_off[k] < 0 ? -op.host_off[k] : op.host_off[k];
+      if (d < tile) continue;
+      const int64_t dt = d / tile;
+      if (d % tile != 0 || dt >= 8 || (dt & (dt - 1)) != 0) plain = false;
+      dmax = std::max(dmax, dt);
+    }
+    if (plain && dmax > 0) {
+      const int r = dmax == 1 ? 1 : dmax == 2 ? 2 : 3;
+      if (p.blocks >= (int64_t(8) << r)) p.map.run_log2 = r;
+    }
+  }
   return p;
 }
 

@@ -56,7 +56,7 @@ class diaq_tuning_t(ctypes.Structure):
     _fields_ = [("spmv_rows", ctypes.c_int32), ("spmv_group_bits", ctypes.c_int32), ("spmv_chunk", ctypes.c_int32),
                 ("spmv_nontemporal", ctypes.c_int32), ("spmv_group_min_qubit", ctypes.c_int32),
                 ("expand_nontemporal", ctypes.c_int32), ("diag_pad", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1), ("spmv_group_qubits", ctypes.c_uint64)]
+                ("spmv_xcd_runs", ctypes.c_int32), ("spmv_group_qubits", ctypes.c_uint64)]
 
 
 class diaq_chain_step_t(ctypes.Structure):

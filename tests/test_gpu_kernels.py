@@ -291,3 +291,29 @@ def test_expect_deterministic():
     psi = to_dev(W.random_state(n, 9))
     vals = {D.expect(H, psi) for _ in range(4)}
     assert len(vals) == 1
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_spmv_xcd_runs_change_only_the_order(dtype):
+    """Gates coupling rows 1, 2 or 4 tiles apart run with XCD-ordered tiles
+    by default: the result must equal the plain launch order bit for bit,
+    and the oracle."""
+    n = 16
+    ctx = D.context()
+    saved = D.get_tuning(ctx)
+    x = W.random_state(n, 8)
+    try:
+        for q in (7, 8, 9, 10, 11, 12):
+            for g in (W.u3(0.4, 1.1, 2.3, q), W.cx(0, q), W.cx(q, 0)):
+                A = D.from_gate(g, n, dtype=dtype)
+                outs = []
+                for knob in (-1, 0):
+                    D.set_tuning(ctx, spmv_xcd_runs=knob)
+                    outs.append(to_host(D.spmv(A, to_dev(x, dtype))))
+                assert np.array_equal(outs[0], outs[1]), "q=%d %s" % (q, g.kind)
+                ref = orc.apply_circuit(x, n, [g])
+                assert np.max(np.abs(outs[1] - ref)) <= (TOL64 if dtype == torch.complex128 else 1e-5)
+    finally:
+        D.set_tuning(ctx, **saved)
+    with pytest.raises(D.DiaqError):
+        D.set_tuning(ctx, spmv_xcd_runs=2)
