@@ -395,9 +395,12 @@ typedef struct diaq_tuning {
                               non-temporal hints; -1: plain stores */
   int32_t diag_pad;        /* elements of padding between the expanded
                               diagonals in the circuit workspace (-1: none) */
-  int32_t spmv_xcd_runs;   /* 0: products whose diagonals couple tiles 1, 2
-                              or 4 apart hand each XCD runs of consecutive
-                              tiles (partner tiles then share an L2);
+  int32_t spmv_xcd_runs;   /* 0: XCD-aware tile order (each XCD has its own
+                              L2): products whose diagonals couple tiles 1,
+                              2 or 4 apart hand each XCD runs of consecutive
+                              tiles, and unpaired products on one coupling
+                              qubit whose partner rows lie >= 16 MiB apart
+                              alternate partner tiles on each XCD;
                               -1: plain launch order */
   uint64_t spmv_group_qubits; /* when non-zero, bit q says whether tiles are
                               paired across coupling qubit q (a per-qubit

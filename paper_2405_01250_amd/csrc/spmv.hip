@@ -44,6 +44,7 @@ struct RowMap {
   int32_t ng;         // number of group bits (0..3)
   int32_t gbit[3];    // ascending qubit indices, each >= tile_log2
   int32_t run_log2;   // XCD runs of 2^run_log2 tiles (0: launch order)
+  int32_t pair_bit;   // > 0: each XCD alternates between tiles differing in this tile bit
 };
 
 // Tile of workgroup b.  The device hands consecutive workgroups to its 8
@@ -53,6 +54,16 @@ struct RowMap {
 // 8 runs; the last partial chunk keeps launch order), and a tile meets its
 // partner less than 2^r tiles away in the same L2.
 __device__ __forceinline__ int64_t tile_of(int64_t b, const RowMap& m) {
+  if (m.pair_bit > 0) {
+    // consecutive workgroups of one XCD take a tile and its partner 2^p
+    // tiles away; the last partial group of 16 keeps launch order
+    const int64_t nb = int64_t(gridDim.x);
+    if (b >= (nb / 16) * 16) return b;
+    const int64_t x = b & 7, u = b >> 3;
+    const int64_t c = ((u >> 1) << 3) | x;
+    const int p = m.pair_bit;
+    return ((c >> p) << (p + 1)) | ((u & 1) << p) | (c & ((int64_t(1) << p) - 1));
+  }
   if (m.run_log2 == 0) return b;
   const int64_t w = int64_t(1) << m.run_log2, chunk = 8 * w;
   if (b >= (int64_t(gridDim.x) / chunk) * chunk) return b;
@@ -398,6 +409,13 @@ struct Plan {
 constexpr int kDefaultRows = 1;
 constexpr int kDefaultGroupMinQubit = 21;
 
+// Partner distance from which far partners are alternated on each XCD:
+// in launch order an XCD reaches a tile's partner D / 8 workgroups later,
+// after about 5 D / 8 tiles of other traffic, which its 4 MB L2 holds up to
+// partners about 16 MiB apart (measured: alternating is slower below that,
+// up to 1.2x faster beyond).
+constexpr int64_t kPairOrderMinBytes = int64_t(16) << 20;
+
 Plan plan_rows(const SpmvOp& op, const diaq_tuning_t& t, int rpt_override) {
   Plan p{};
   const int n = op.n;
@@ -467,6 +485,22 @@ Plan plan_rows(const SpmvOp& op, const diaq_tuning_t& t, int rpt_override) {
       const int r = dmax == 1 ? 1 : dmax == 2 ? 2 : 3;
       if (p.blocks >= (int64_t(8) << r)) p.map.run_log2 = r;
     }
+  }
+  // far partners (one coupling qubit whose tiles are >= 2^3 apart, not
+  // paired inside a workgroup): alternate partner tiles on each XCD
+  if (nb == 0 && op.nd <= kMaxArgDiags && t.spmv_xcd_runs >= 0 && p.map.run_log2 == 0) {
+    int pb = -1, cnt = 0;
+    for (int q = tile_log2 + 3; q < n; q++)
+      if ((op.qubit_mask >> q) & 1) {
+        pb = q - tile_log2;
+        cnt++;
+      }
+    int low = 0;
+    for (int q = 0; q < tile_log2 + 3 && q < n; q++) low += ((op.qubit_mask >> q) & 1) && q >= tile_log2 ? 1 : 0;
+    const int64_t tile_bytes = (int64_t(1) << tile_log2) * int64_t(elem_bytes(op.dtype));
+    if (cnt == 1 && low == 0 && (int64_t(1) << pb) * 2 <= p.blocks && p.blocks >= 16 &&
+        (tile_bytes << pb) >= kPairOrderMinBytes)
+      p.map.pair_bit = pb;
   }
   return p;
 }

@@ -317,3 +317,28 @@ def test_spmv_xcd_runs_change_only_the_order(dtype):
         D.set_tuning(ctx, **saved)
     with pytest.raises(D.DiaqError):
         D.set_tuning(ctx, spmv_xcd_runs=2)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_spmv_far_partner_order_changes_only_the_order(dtype):
+    """Gates whose partner rows lie 16 MiB or more apart alternate partner
+    tiles on each XCD by default: bitwise the plain launch order, and the
+    oracle (n = 22, 4-KiB tiles: qubits 20 and 21)."""
+    n = 22
+    ctx = D.context()
+    saved = D.get_tuning(ctx)
+    x = W.random_state(n, 9)
+    try:
+        D.set_tuning(ctx, spmv_group_bits=-1)  # no pairing inside a workgroup
+        for q in (19, 20, 21):
+            for g in (W.u3(0.4, 1.1, 2.3, q), W.cx(3, q)):
+                A = D.from_gate(g, n, dtype=dtype)
+                outs = []
+                for knob in (-1, 0):
+                    D.set_tuning(ctx, spmv_xcd_runs=knob)
+                    outs.append(to_host(D.spmv(A, to_dev(x, dtype))))
+                assert np.array_equal(outs[0], outs[1]), "q=%d %s" % (q, g.kind)
+                ref = orc.apply_circuit(x, n, [g])
+                assert np.max(np.abs(outs[1] - ref)) <= (TOL64 if dtype == torch.complex128 else 1e-5)
+    finally:
+        D.set_tuning(ctx, **saved)
