@@ -241,19 +241,19 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(DiagArgs da, DiagSrc src, 
 }
 
 // In-place variant for matrices whose only diagonal is the principal one.
-template <typename R>
+template <typename R, bool NT>
 __global__ __launch_bounds__(kBlock) void diag_inplace_kernel(int64_t N, int32_t conjugate,
                                                               const typename Vec<R>::V* __restrict__ vals,
                                                               typename Vec<R>::V* xy) {
   using V = typename Vec<R>::V;
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
-    V v = vals[i];
+    V v = ld<NT>(vals + i);
     if (conjugate) v.y = -v.y;
-    const V a = xy[i];
+    const V a = ld<NT>(xy + i);
     V r{0, 0};
     cfma<R>(r, v, a);
-    xy[i] = r;
+    st<NT>(xy + i, r);
   }
 }
 
@@ -591,12 +591,15 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
     if (!(op.nd == 1 && op.host_off[0] == 0))
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "x and y alias for a matrix with off-principal diagonals");
     const int64_t blocks = (N + kBlock - 1) / kBlock;  // one element per lane
+    // complex128 streams with non-temporal hints (measured 5.76 -> 6.32
+    // TB/s at n = 28); complex64 is faster with plain accesses (5.95 against
+    // 5.03 TB/s)
     if (op.dtype == DIAQ_C128)
-      hipLaunchKernelGGL(diag_inplace_kernel<double>, dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream, N,
-                         op.conjugate ? 1 : 0, static_cast<const double2*>(op.values), static_cast<double2*>(y));
+      hipLaunchKernelGGL((diag_inplace_kernel<double, true>), dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream,
+                         N, op.conjugate ? 1 : 0, static_cast<const double2*>(op.values), static_cast<double2*>(y));
     else
-      hipLaunchKernelGGL(diag_inplace_kernel<float>, dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream, N,
-                         op.conjugate ? 1 : 0, static_cast<const float2*>(op.values), static_cast<float2*>(y));
+      hipLaunchKernelGGL((diag_inplace_kernel<float, false>), dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream,
+                         N, op.conjugate ? 1 : 0, static_cast<const float2*>(op.values), static_cast<float2*>(y));
     DIAQ_HIP(hipGetLastError());
     return DIAQ_OK;
   }
