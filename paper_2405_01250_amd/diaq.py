@@ -540,8 +540,10 @@ def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: in
 
 
 def set_tuning(ctx: Context | None = None, **knobs):
-    """Set product-kernel knobs (spmv_rows, spmv_group_bits, spmv_chunk,
-    spmv_nontemporal); unnamed knobs keep their current value."""
+    """Set product-kernel knobs (the fields of diaq_tuning_t: spmv_rows,
+    spmv_group_bits, spmv_chunk, spmv_nontemporal, spmv_group_min_qubit,
+    expand_nontemporal, diag_pad, spmv_xcd_runs, spmv_group_qubits);
+    unnamed knobs keep their current value."""
     ctx = ctx or context()
     t = diaq_tuning_t()
     _check(load().diaq_get_tuning(ctx.handle, ctypes.byref(t)))
