@@ -392,7 +392,9 @@ typedef struct diaq_tuning {
                               partner rows are too far apart in launch
                               order to meet in the caches) */
   int32_t expand_nontemporal; /* 1: write expanded diagonals with
-                              non-temporal hints; -1: plain stores */
+                              non-temporal hints; -1: plain stores;
+                              0: hints for complex64 only (measured the
+                              faster choice for each type) */
   int32_t diag_pad;        /* elements of padding between the expanded
                               diagonals in the circuit workspace (-1: none) */
   int32_t spmv_xcd_runs;   /* 0: XCD-aware tile order (each XCD has its own

@@ -186,7 +186,10 @@ diaq_status_t launch_expand(diaq_ctx* ctx, const LocalGate& lg, int n, diaq_dtyp
   const int64_t per_block = int64_t(kBlock) * (dt == DIAQ_C64 ? 2 : 1);
   const int64_t gx = (maxlen + per_block - 1) / per_block;
   dim3 grid(unsigned(gx), unsigned(offs.size()));
-  const bool nt = ctx->tuning.expand_nontemporal > 0;
+  // default: non-temporal stores for complex64 (measured 6.1 -> 6.5 TB/s at
+  // n = 28), plain ones for complex128 (6.83 against 6.76 TB/s)
+  const int32_t knob = ctx->tuning.expand_nontemporal;
+  const bool nt = knob > 0 || (knob == 0 && dt == DIAQ_C64);
   if (dt == DIAQ_C128) {
     if (nt)
       hipLaunchKernelGGL((expand_kernel<double, true>), grid, dim3(kBlock), 0, ctx->stream, a,
