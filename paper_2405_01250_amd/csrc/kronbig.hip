@@ -128,7 +128,7 @@ bool make_factor(const LocalGate& lg, DiagFactor* f) {
 struct BigArgs {
   int64_t ncos;
   int32_t nt;
-  int32_t pad;
+  int32_t nt_io;     // non-temporal state streams
   int32_t sorted[5];
   int32_t pad2;
   int64_t off[32];  // global offset of local index r
@@ -146,6 +146,30 @@ template <>
 struct Vec<float> {
   using V = float2;
 };
+
+// State loads and stores, with non-temporal hints when nt (each amplitude
+// is read and written once per operation).
+template <typename V>
+__device__ __forceinline__ V bld(const V* p, bool nt) {
+  if (nt) {
+    typedef decltype(V{}.x) E;
+    typedef E N2 __attribute__((ext_vector_type(2)));
+    const N2 t = __builtin_nontemporal_load(reinterpret_cast<const N2*>(p));
+    return V{t[0], t[1]};
+  }
+  return *p;
+}
+template <typename V>
+__device__ __forceinline__ void bst(V* p, const V& v, bool nt) {
+  if (nt) {
+    typedef decltype(V{}.x) E;
+    typedef E N2 __attribute__((ext_vector_type(2)));
+    N2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<N2*>(p));
+  } else {
+    *p = v;
+  }
+}
 
 template <typename R, int K>
 __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename Vec<R>::V* __restrict__ v) {
@@ -165,7 +189,7 @@ __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename
   double xr[D], xi[D];
 #pragma unroll
   for (int r = 0; r < D; r++) {
-    const V t = v[base + a.off[r]];
+    const V t = bld(v + base + a.off[r], a.nt_io != 0);
     xr[r] = double(t.x);
     xi[r] = double(t.y);
   }
@@ -185,7 +209,7 @@ __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename
     double yi = (pi[0] + pi[1]) + (pi[2] + pi[3]);
     const int64_t i = base + a.off[r];
     if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(i), yr, yi);
-    v[i] = V{R(yr), R(yi)};
+    bst(v + i, V{R(yr), R(yi)}, a.nt_io != 0);
   }
 }
 
@@ -222,7 +246,7 @@ struct LdsArgs {
   int32_t swz;
   int32_t smask;
   int32_t nt;
-  int32_t pad0;
+  int32_t nt_io;     // non-temporal state streams
   int64_t lane_off[kLdsCosetBits];  // element offset of lane bit i
   int32_t lane_e[kLdsCosetBits];    // staging bit of lane bit i
   int32_t pad;
@@ -273,7 +297,7 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
   {
     V t[L];
 #pragma unroll
-    for (int j = 0; j < L; j++) t[j] = v[tid_el + a.joff[j * PARTS]];
+    for (int j = 0; j < L; j++) t[j] = bld(v + tid_el + a.joff[j * PARTS], a.nt_io != 0);
 #pragma unroll
     for (int j = 0; j < L; j++) sx[slot(a, tid + j * T)] = double2{double(t[j].x), double(t[j].y)};
   }
@@ -317,7 +341,7 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
 #pragma unroll
     for (int j = 0; j < L; j++) t[j] = sx[slot(a, tid + j * T)];
 #pragma unroll
-    for (int j = 0; j < L; j++) v[tid_el + a.joff[j * PARTS]] = V{R(t[j].x), R(t[j].y)};
+    for (int j = 0; j < L; j++) bst(v + tid_el + a.joff[j * PARTS], V{R(t[j].x), R(t[j].y)}, a.nt_io != 0);
   }
 }
 
@@ -493,12 +517,17 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
     const char* tk = nt ? base + mb + tabs.first[k] : nullptr;
     const size_t e0 = prof_mark(ctx);
     LdsArgs la;
+    // complex128 state streams with non-temporal hints up to four qubits
+    // (layered n = 28, groups of 4: 163 -> 155 ms); five-qubit groups
+    // measured faster without
+    const int ntp = (op.k <= 4 && dt == DIAQ_C128) ? 1 : 0;
     if (op.raw) {
       DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, op.lg, n, dt, state, false, tk, nt));
     } else if (staged(op.q, op.k) && make_lds_args(op.q, op.k, n, &la)) {
       la.mat = dm + moff[k];
       la.tabs = tk;
       la.nt = nt;
+      la.nt_io = ntp;
       if (dt == DIAQ_C128) launch_lds<double>(la, op.k, n, ctx->stream, state);
       else launch_lds<float>(la, op.k, n, ctx->stream, state);
       DIAQ_HIP(hipGetLastError());
@@ -525,6 +554,7 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
       std::memset(&a, 0, sizeof(a));
       a.ncos = N >> op.k;
       a.nt = nt;
+      a.nt_io = ntp;
       for (int j = 0; j < op.k; j++) a.sorted[j] = op.q[j];
       for (int r = 0; r < (1 << op.k); r++) {
         int64_t o = 0;
