@@ -226,3 +226,28 @@ def test_fused_qft_n20_against_ifft():
     psi = to_dev(x)
     D.apply_circuit(W.qft(n), psi, plan=D.make_plan(fuse=True, max_fused_qubits=2))
     assert_state_close(to_host(psi), np.fft.ifft(x, norm="ortho"), TOL64, "fused QFT-20")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_every_plan_and_graph_agree_n20(seed):
+    """A random circuit of every gate shape (controls, custom matrices,
+    gates on the lowest and highest qubits) at n = 20 under every plan, and
+    replayed from a circuit graph, against the oracle."""
+    rng = np.random.default_rng(2000 + seed)
+    n = 20
+    gates = [_random_gate(rng, n) for _ in range(60)]
+    gates += [W.u3(0.3, 0.7, 1.1, 0), W.u3(0.2, 0.5, 0.9, n - 1), W.cx(n - 1, 0), W.cp(0.4, 1, n - 2)]
+    x = W.random_state(n, seed)
+    want = orc.apply_circuit(x, n, gates)
+    plans = [None, D.make_plan(fuse=True, max_fused_qubits=2), D.make_plan(fuse=True, max_fused_qubits=3),
+             D.make_plan(kron=True)] + [D.make_plan(kron=True, fuse=True, max_fused_qubits=k) for k in (2, 3, 4, 5)]
+    for i, plan in enumerate(plans):
+        psi = to_dev(x)
+        D.apply_circuit(gates, psi, plan=plan)
+        assert_state_close(to_host(psi), want, TOL64, "seed %d plan %d" % (seed, i))
+    psi = to_dev(x)
+    g = D.CircuitGraph(gates, psi, plan=plans[-1])
+    g.launch()
+    torch.cuda.synchronize()
+    assert_state_close(to_host(psi), want, TOL64, "seed %d graph" % seed)
+    g.close()
