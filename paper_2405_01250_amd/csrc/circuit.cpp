@@ -72,6 +72,13 @@ diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t
   op.transpose = adjoint;
   op.conjugate = adjoint;
   op.qubit_mask = lg.tmask;
+  if (offs.empty()) {
+    // a gate whose matrix is all zero: y = 0 (a fill kernel, no memset node
+    // in a recorded graph)
+    DIAQ_TRY(launch_zero(ctx->stream, *y, size_t(int64_t(1) << n) * elem_bytes(dt)));
+    std::swap(*x, *y);
+    return DIAQ_OK;
+  }
   if (offs.size() == 1 && offs[0] == 0) return launch_spmv(ctx, op, *x, *x);
   DIAQ_TRY(launch_spmv(ctx, op, *x, *y));
   std::swap(*x, *y);

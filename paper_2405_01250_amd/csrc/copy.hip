@@ -1,6 +1,8 @@
 // copy.hip -- device-to-device copy by a streaming kernel: the circuit
 // drivers' state copies (scratch -> state, psi0 -> psi) and, exported as
-// diaq_copy, the plain-copy reference of the bandwidth measurements.
+// diaq_copy, the plain-copy reference of the bandwidth measurements; and a
+// zero fill (a kernel rather than a memset, so that recorded circuit graphs
+// hold no memset node).
 #include "internal.hpp"
 
 namespace diaq {
@@ -21,7 +23,24 @@ __global__ __launch_bounds__(kBlock) void copy16_kernel(int64_t n16, const doubl
   }
 }
 
+__global__ __launch_bounds__(kBlock) void zero16_kernel(int64_t n16, double2* __restrict__ dst) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n16) dst[i] = double2{0.0, 0.0};
+}
+
 }  // namespace
+
+diaq_status_t launch_zero(hipStream_t stream, void* dst, size_t bytes) {
+  if (bytes == 0) return DIAQ_OK;
+  if ((reinterpret_cast<uintptr_t>(dst) | bytes) & 15)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "fill needs a 16-byte aligned pointer and a multiple of 16 bytes");
+  const int64_t n16 = int64_t(bytes / 16);
+  const int64_t blocks = (n16 + kBlock - 1) / kBlock;
+  if (blocks > 0x7fffffffLL) return fail(DIAQ_ERR_UNSUPPORTED, "fill of %zu bytes", bytes);
+  hipLaunchKernelGGL(zero16_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, n16, static_cast<double2*>(dst));
+  DIAQ_HIP(hipGetLastError());
+  return DIAQ_OK;
+}
 
 diaq_status_t launch_copy(hipStream_t stream, const void* src, void* dst, size_t bytes) {
   if (bytes == 0) return DIAQ_OK;

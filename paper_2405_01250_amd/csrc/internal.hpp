@@ -449,6 +449,8 @@ diaq_status_t ensure(diaq_ctx* ctx, Workspace* w, size_t bytes);
 // Device-to-device copy by a streaming kernel (16-byte aligned, a multiple
 // of 16 bytes, no overlap).
 diaq_status_t launch_copy(hipStream_t stream, const void* src, void* dst, size_t bytes);
+// dst <- 0 by a kernel (16-byte aligned, a multiple of 16 bytes).
+diaq_status_t launch_zero(hipStream_t stream, void* dst, size_t bytes);
 // Copy a host table that dies with the calling function into device memory
 // ahead of the launches that read it: synchronous (after the stream's
 // earlier work) when running eagerly, a copy node from pinned staging when

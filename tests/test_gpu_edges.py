@@ -107,3 +107,26 @@ def test_device_copy():
         D.copy(raw[:2048], raw[1024:3072])  # overlap
     torch.cuda.synchronize()
     assert bool(torch.all(dst == 1))
+
+
+@pytest.mark.parametrize("kw", PLANS)
+def test_all_zero_gate_matrix(kw):
+    """A custom gate whose matrix is all zero has no stored diagonal: the
+    state becomes zero on every plan, eagerly and replayed from a graph
+    (which then holds a fill kernel, not a memset node)."""
+    n = 9
+    gates = [W.h(0), W.Gate("MATRIX", (3,), (), matrix=np.zeros((2, 2))), W.h(2)]
+    x = W.random_state(n, 12)
+    want = orc.apply_circuit(x, n, gates)
+    assert not np.any(want)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi, plan=_plan(kw))
+    assert not np.any(to_host(psi))
+    psi = to_dev(x)
+    g = D.CircuitGraph(gates, psi, plan=_plan(kw))
+    for _ in range(2):
+        psi.copy_(to_dev(x))
+        g.launch()
+        torch.cuda.synchronize()
+        assert not np.any(to_host(psi))
+    g.close()
