@@ -145,21 +145,43 @@ diaq_status_t run_fused(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, d
 }
 
 // Alg. 3 forward pass: every op applied in place on `state`, no expansion.
+// Operations on the lowest qubits are staged through LDS as dense groups.
 diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, diaq_dtype_t dt, void* state) {
   OpTables tabs;
   for (const FusedOp& op : ops) tabs.add(op.post);
-  const char* dtab = nullptr;
-  if (!tabs.bytes.empty()) {
-    DIAQ_TRY(ensure(ctx, &ctx->aux, tabs.bytes.size()));
-    dtab = static_cast<const char*>(ctx->aux.ptr);
-    DIAQ_TRY(upload(ctx, ctx->aux.ptr, tabs.bytes.data(), tabs.bytes.size()));
+  struct Staged {
+    int S[6];
+    int k = 0;
+    size_t moff = 0;
+  };
+  std::vector<Staged> stg(ops.size());
+  std::vector<double> mats, m;
+  for (size_t k = 0; k < ops.size(); k++) {
+    if (!staged_dense(ops[k].core, n, tabs.count[k], &m, stg[k].S, &stg[k].k)) continue;
+    stg[k].moff = mats.size();
+    mats.insert(mats.end(), m.begin(), m.end());
   }
+  const size_t mb = ((mats.size() * sizeof(double) + 255) / 256) * 256;
+  char* base = nullptr;
+  if (mb + tabs.bytes.size()) {
+    DIAQ_TRY(ensure(ctx, &ctx->aux, mb + tabs.bytes.size()));
+    base = static_cast<char*>(ctx->aux.ptr);
+    DIAQ_TRY(upload(ctx, base, mats.data(), mats.size() * sizeof(double)));
+    DIAQ_TRY(upload(ctx, base + mb, tabs.bytes.data(), tabs.bytes.size()));
+  }
+  const double full = 2.0 * double(elem_bytes(dt)) * double(int64_t(1) << n);
   for (size_t k = 0; k < ops.size(); k++) {
     const int nt = tabs.count[k];
+    const char* tk = nt ? base + mb + tabs.first[k] : nullptr;
     const size_t e0 = prof_mark(ctx);
-    DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false,
-                               nt ? dtab + tabs.first[k] : nullptr, nt));
-    prof_interval(ctx, e0, prof_mark(ctx), 1, kron_op_bytes(ops[k].core, int(ops[k].post.size()), n, dt));
+    if (stg[k].k) {
+      DIAQ_TRY(launch_staged(ctx, stg[k].S, stg[k].k, reinterpret_cast<const double*>(base) + stg[k].moff, tk, nt, n,
+                             dt, state));
+      prof_interval(ctx, e0, prof_mark(ctx), 1, full);
+    } else {
+      DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false, tk, nt));
+      prof_interval(ctx, e0, prof_mark(ctx), 1, kron_op_bytes(ops[k].core, int(ops[k].post.size()), n, dt));
+    }
   }
   return DIAQ_OK;
 }

@@ -265,6 +265,14 @@ diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax
 // Applies the operations in place (each one read and one write of the
 // state), with profiling intervals of 2 s N bytes per operation.
 diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_dtype_t dt, void* state);
+// An Alg. 3 operation of at most four qubits (targets and controls) that
+// touches the lowest qubits runs faster staged through LDS as a dense
+// group: true with the dense matrix (interleaved, over the sorted qubits S,
+// k of them) if lg qualifies at n qubits (`tables`: it carries factor
+// tables).  launch_staged then applies it in place.
+bool staged_dense(const LocalGate& lg, int n, int tables, std::vector<double>* mat, int* S, int* k);
+diaq_status_t launch_staged(diaq_ctx* ctx, const int* S, int k, const double* dmat, const char* tabs, int nt, int n,
+                            diaq_dtype_t dt, void* state);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (one .hip file each)

@@ -415,6 +415,42 @@ void launch_lds(const LdsArgs& a, int k, int n, hipStream_t stream, void* state)
 
 }  // namespace
 
+bool staged_dense(const LocalGate& lg, int n, int tables, std::vector<double>* mat, int* S, int* k) {
+  // uncontrolled operations, or ones whose factors touch every row anyway
+  // (a controlled one without them reads only its control-on half)
+  if (lg.nc && !tables) return false;
+  int q[6];
+  const int u = gate_qubit_list(lg, q);
+  if (u > 4) return false;
+  std::sort(q, q + u);
+  if (!staged(q, u)) return false;
+  LdsArgs probe;
+  if (!make_lds_args(q, u, n, &probe)) return false;
+  const std::vector<Cd> E = embed_gate(lg, q, u);
+  mat->resize(2 * E.size());
+  for (size_t i = 0; i < E.size(); i++) {
+    (*mat)[2 * i] = E[i].real();
+    (*mat)[2 * i + 1] = E[i].imag();
+  }
+  for (int j = 0; j < u; j++) S[j] = q[j];
+  *k = u;
+  return true;
+}
+
+diaq_status_t launch_staged(diaq_ctx* ctx, const int* S, int k, const double* dmat, const char* tabs, int nt, int n,
+                            diaq_dtype_t dt, void* state) {
+  LdsArgs la;
+  if (!make_lds_args(S, k, n, &la)) return fail(DIAQ_ERR_UNSUPPORTED, "staged group of %d qubits at n = %d", k, n);
+  la.mat = dmat;
+  la.tabs = tabs;
+  la.nt = tabs ? nt : 0;
+  la.nt_io = (k <= 4 && dt == DIAQ_C128) ? 1 : 0;
+  if (dt == DIAQ_C128) launch_lds<double>(la, k, n, ctx->stream, state);
+  else launch_lds<float>(la, k, n, ctx->stream, state);
+  DIAQ_HIP(hipGetLastError());
+  return DIAQ_OK;
+}
+
 diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops) {
   if (kmax < 1 || kmax > 5) return fail(DIAQ_ERR_INVALID_ARGUMENT, "max_fused_qubits must be 1..5");
   ops->clear();
