@@ -706,7 +706,6 @@ diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan&
   // one launch after the sweep
   char* t = static_cast<char*>(table_mem);
   const size_t gb = ((P.gates.size() * sizeof(SegGate) + 255) / 256) * 256;
-  const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
   const SegGate* dg = reinterpret_cast<const SegGate*>(t);
   const double* dp = reinterpret_cast<const double*>(t + gb);
   const int64_t blocks = segment_blocks(n);

@@ -180,3 +180,32 @@ def test_kron_staged_low_qubit_groups(S):
         psi32 = to_dev(x, torch.complex64)
         D.apply_circuit(gates, psi32, plan=D.make_plan(kron=True, fuse=True, max_fused_qubits=5))
         assert_state_close(to_host(psi32), orc.apply_circuit(x, n, gates), TOL32, "S=%s n=%d c64" % (S, n))
+
+
+@pytest.mark.parametrize("kmax", [2, 3, 4, 5])
+def test_factor_tables_on_wave_varying_and_uniform_qubits(kmax):
+    """Operations whose folded diagonal factors sit on the lowest qubits
+    (which differ across a wave's cosets), on high qubits only (the same for
+    a whole wave), or on both, with plain and controlled cores: every table
+    class against the oracle, complex128 and complex64."""
+    n = 15
+    rng = np.random.default_rng(70 + kmax)
+    gates = []
+    for t in (14, 13, 12, 2, 0):
+        gates.append(W.h(t))
+        for k in range(n):
+            if k != t and rng.random() < 0.7:
+                gates.append(W.cp(float(rng.uniform(0, 6)), k, t))
+        gates += [W.Gate("RZZ", (9, 11), (), (0.37,)), W.Gate("RZ", (1,), (), (1.1,)), W.cz(3, 10),
+                  W.cp(0.2, 4, 8)]
+    gates += [W.cx(12, 14), W.cp(0.9, 1, 14), W.cp(0.4, 10, 14), W.Gate("RZZ", (9, 10), (), (0.8,)),
+              W.cx(5, 13), W.cp(1.3, 0, 13), W.cz(7, 11)]
+    x = W.random_state(n, 71)
+    ref = orc.apply_circuit(x, n, gates)
+    plan = D.make_plan(kron=True, fuse=True, max_fused_qubits=kmax)
+    psi = to_dev(x)
+    D.apply_circuit(gates, psi, plan=plan)
+    assert_state_close(to_host(psi), ref, TOL64, "kmax=%d" % kmax)
+    psi32 = to_dev(x, torch.complex64)
+    D.apply_circuit(gates, psi32, plan=plan)
+    assert_state_close(to_host(psi32), ref, TOL32, "kmax=%d c64" % kmax, l2tol=1e-4)
