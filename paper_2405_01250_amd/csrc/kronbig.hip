@@ -10,7 +10,7 @@
 // 2^k x 2^k matrix (controls are qubits of the group).  Diagonal gates that
 // do not fit stay row factors of an operation.  A lane owns one coset of the
 // group (Alg. 3's cosets), keeps its 2^k amplitudes in registers, reads the
-// matrix from LDS and writes each output row as soon as it is formed.
+// matrix by scalar loads and writes each output row as soon as it is formed.
 #include <complex>
 
 #include "internal.hpp"
@@ -175,9 +175,13 @@ template <typename R, int K>
 __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename Vec<R>::V* __restrict__ v) {
   using V = typename Vec<R>::V;
   constexpr int D = 1 << K;
-  __shared__ double2 sm[D * D];
-  for (int t = threadIdx.x; t < D * D; t += kBigBlock) sm[t] = double2{a.mat[2 * t], a.mat[2 * t + 1]};
-  __syncthreads();
+  // the matrix through the constant address space: every lane reads the
+  // same entry at the same time, so these are scalar loads into SGPRs that
+  // feed the FMAs directly (staging it in LDS made the LDS-to-register
+  // traffic, 16 B per lane per entry, the limit: layered n = 28 with
+  // 5-qubit groups 157 -> 150 ms, TFIM-28 313 -> 292 ms)
+  typedef __attribute__((address_space(4))) const double GD;
+  GD* mp = (GD*)(a.mat);
   const int64_t c = int64_t(blockIdx.x) * kBigBlock + threadIdx.x;
   if (c >= a.ncos) return;
   int64_t base = c;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename
     double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int q = 0; q < D; q++) {
-      const double2 m = sm[r * D + q];
+      const double2 m = double2{mp[2 * (r * D + q)], mp[2 * (r * D + q) + 1]};
       pr[q & 3] = fma(m.x, xr[q], fma(-m.y, xi[q], pr[q & 3]));
       pi[q & 3] = fma(m.x, xi[q], fma(m.y, xr[q], pi[q & 3]));
     }
@@ -280,10 +284,13 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
   constexpr int E = kLdsLanes * D;
   constexpr int T = kLdsLanes * PARTS;  // lanes per block
   constexpr int L = D / PARTS;           // loads per lane, rows per lane
-  __shared__ double2 sm[D * D];
   __shared__ double2 sx[E];
   const int tid = threadIdx.x;
-  for (int t = tid; t < D * D; t += T) sm[t] = double2{a.mat[2 * t], a.mat[2 * t + 1]};
+  // the matrix by scalar loads, as in kron_big_kernel: a wave's rows are
+  // uniform (its part index, read while every lane is active)
+  typedef __attribute__((address_space(4))) const double GD;
+  GD* mp = (GD*)(a.mat);
+  const int part = __builtin_amdgcn_readfirstlane(tid / kLdsLanes);
   int64_t base = blockIdx.x;
   for (int j = 0; j < a.npos; j++) {
     const int p = a.pos[j];
@@ -302,7 +309,7 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
     for (int j = 0; j < L; j++) sx[slot(a, tid + j * T)] = double2{double(t[j].x), double(t[j].y)};
   }
   __syncthreads();
-  const int lane = tid & (kLdsLanes - 1), part = tid / kLdsLanes;
+  const int lane = tid & (kLdsLanes - 1);
   int el = 0;
   int64_t lo = 0;
 #pragma unroll
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
     double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int q = 0; q < D; q++) {
-      const double2 m = sm[r * D + q];
+      const double2 m = double2{mp[2 * (r * D + q)], mp[2 * (r * D + q) + 1]};
       pr[q & 3] = fma(m.x, xr[q], fma(-m.y, xi[q], pr[q & 3]));
       pi[q & 3] = fma(m.x, xi[q], fma(m.y, xr[q], pi[q & 3]));
     }
