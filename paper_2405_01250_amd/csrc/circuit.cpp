@@ -147,8 +147,6 @@ diaq_status_t run_fused(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, d
 // Alg. 3 forward pass: every op applied in place on `state`, no expansion.
 // Operations on the lowest qubits are staged through LDS as dense groups.
 diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, diaq_dtype_t dt, void* state) {
-  OpTables tabs;
-  for (const FusedOp& op : ops) tabs.add(op.post);
   struct Staged {
     int S[6];
     int k = 0;
@@ -156,10 +154,18 @@ diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, di
   };
   std::vector<Staged> stg(ops.size());
   std::vector<double> mats, m;
+  OpTables tabs;
   for (size_t k = 0; k < ops.size(); k++) {
-    if (!staged_dense(ops[k].core, n, tabs.count[k], &m, stg[k].S, &stg[k].k)) continue;
-    stg[k].moff = mats.size();
-    mats.insert(mats.end(), m.begin(), m.end());
+    if (staged_dense(ops[k].core, n, int(ops[k].post.size()), &m, stg[k].S, &stg[k].k)) {
+      stg[k].moff = mats.size();
+      mats.insert(mats.end(), m.begin(), m.end());
+      tabs.add(ops[k].post);
+    } else {
+      // per-coset kernel: table headers carry the rows' index bits
+      int64_t off[8];
+      kron_row_offsets(ops[k].core, off);
+      tabs.add(ops[k].post, off, 1 << ops[k].core.k);
+    }
   }
   const size_t mb = ((mats.size() * sizeof(double) + 255) / 256) * 256;
   char* base = nullptr;
@@ -179,7 +185,7 @@ diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, di
                              dt, state));
       prof_interval(ctx, e0, prof_mark(ctx), 1, full);
     } else {
-      DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false, tk, nt));
+      DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, ops[k].core, n, dt, state, false, tk, nt, nullptr, true));
       prof_interval(ctx, e0, prof_mark(ctx), 1, kron_op_bytes(ops[k].core, int(ops[k].post.size()), n, dt));
     }
   }

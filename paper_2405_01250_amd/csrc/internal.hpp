@@ -183,11 +183,16 @@ struct TableHead {
   int32_t nq;       // qubits of the table
   int32_t nruns;    // runs of consecutive qubits; none crosses bit 32
   int32_t run[10];  // first qubit | length << 8 | first index bit << 16
+  int32_t roff[8];  // index bits of the operation's row offsets off[r]
 };
-static_assert(sizeof(TableHead) == 48, "table header is 48 bytes");
+static_assert(sizeof(TableHead) == 80, "table header is 80 bytes");
 inline size_t table_bytes(int nq) { return sizeof(TableHead) + (size_t(16) << nq); }
 // Appends the tables of f[0..nf) to *out (planner.cpp); returns how many.
-int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out);
+// With row offsets off[0..noff) (noff <= 8; the element offsets of an
+// operation's local rows, on bits its cosets leave 0), each header also
+// holds roff[r] = the table index bits of off[r].
+int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out, const int64_t* off = nullptr,
+                    int noff = 0);
 
 // (vr, vi) *= the product of the nt tables at `tabs` at element i.
 __device__ __forceinline__ void apply_tables(const char* tabs, int nt, uint64_t i, double& vr, double& vi) {
@@ -217,15 +222,51 @@ __device__ __forceinline__ void apply_tables(const char* tabs, int nt, uint64_t 
   }
 }
 
+// Rows base | off[r], r < D, of a coset whose tables were compiled with
+// those row offsets: (vr[r], vi[r]) *= the product of the nt tables.  A
+// table's header is decoded once for all D rows: the coset's index bits
+// come from base, each row ORs in the header's roff[r] (the bit gather is
+// linear over disjoint bits).
+template <int D>
+__device__ __forceinline__ void apply_tables_rows(const char* tabs, int nt, uint64_t base, double (&vr)[D],
+                                                  double (&vi)[D]) {
+  typedef __attribute__((address_space(4))) const char GChar;
+  typedef __attribute__((address_space(4))) const TableHead GHead;
+  typedef __attribute__((address_space(4))) const double GDouble;
+  const uint32_t lo = uint32_t(base), hi = uint32_t(base >> 32);
+  GChar* p = (GChar*)(tabs);
+  for (int t = 0; t < nt; t++) {
+    GHead* h = (GHead*)(p);
+    const int nq = h->nq, nr = h->nruns;
+    uint32_t idx = 0;
+    for (int q = 0; q < nr; q++) {
+      const uint32_t w = uint32_t(h->run[q]);
+      const uint32_t src = w & 63u, len = (w >> 8) & 15u, dst = (w >> 16) & 15u;
+      const uint32_t word = src < 32u ? lo : hi;
+      idx |= ((word >> (src & 31u)) & ((1u << len) - 1u)) << dst;
+    }
+    GDouble* e = (GDouble*)(p + sizeof(TableHead));
+#pragma unroll
+    for (int r = 0; r < D; r++) {
+      const uint32_t ir = idx | uint32_t(h->roff[r]);
+      const double fr = e[2 * ir], fi = e[2 * ir + 1];
+      const double nr2 = vr[r] * fr - vi[r] * fi;
+      vi[r] = vr[r] * fi + vi[r] * fr;
+      vr[r] = nr2;
+    }
+    p += sizeof(TableHead) + (size_t(16) << nq);
+  }
+}
+
 // Device tables of several operations' factors in one buffer: op k's tables
 // start at byte first[k] and number count[k].
 struct OpTables {
   std::vector<char> bytes;
   std::vector<size_t> first;
   std::vector<int> count;
-  void add(const std::vector<DiagFactor>& post) {
+  void add(const std::vector<DiagFactor>& post, const int64_t* off = nullptr, int noff = 0) {
     first.push_back(bytes.size());
-    count.push_back(post.empty() ? 0 : compile_factors(post.data(), int(post.size()), &bytes));
+    count.push_back(post.empty() ? 0 : compile_factors(post.data(), int(post.size()), &bytes, off, noff));
   }
 };
 
@@ -330,9 +371,14 @@ diaq_status_t launch_generator_dot(diaq_ctx* ctx, const LocalGate& gen, int n,
 // kron.hip: Alg. 3 products without expansion, in place on `v`.  `dmat`
 // (device, 4 x 4 complex, at most 2 targets) replaces lg's matrix when the
 // matrix depends on angles that live on the device.
+// `rows`: the tables were compiled with the row offsets kron_row_offsets
+// gives for lg (one header decode per coset instead of one per row).
 diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
                                 void* v, bool adjoint, const void* tabs = nullptr, int nt = 0,
-                                const double* dmat = nullptr);
+                                const double* dmat = nullptr, bool rows = false);
+// off[r] (r < 2^lg.k): the element offset of local row r (bit j of r on
+// qubit lg.targets[j]), as the Alg. 3 kernels address a coset's rows.
+void kron_row_offsets(const LocalGate& lg, int64_t* off);
 // Reverse-sweep step: optional generator dot (one double2 partial per
 // workgroup into `partial`, kron_adjoint_blocks of them), then
 // psi, lam <- U^dagger psi, U^dagger lam when step_back.

@@ -41,6 +41,8 @@ struct KronArgs {
   uint64_t cmask;
   int32_t adjoint;
   int32_t nt;          // folded diagonal factors: tables at tabs
+  int32_t rows;        // 1: the table headers hold this op's roff[r]
+  int32_t pad;
   const char* tabs;
   const double* dmat;  // device 4 x 4 local matrix (k <= 2), replaces m
   double m[8][8][2];
@@ -86,7 +88,9 @@ __device__ __forceinline__ void mat_vec(const KronArgs& a, const double (&xr)[1 
 
 // In place: v <- (M or M^dagger) v on every coset whose controls are 1,
 // then the folded diagonal factors.
-template <typename R, int K, bool DM>
+// TAB: 1 factor tables (if any) looked up row by row, 2 tables whose
+// headers hold the rows' index bits (one header decode per coset).
+template <typename R, int K, bool DM, int TAB>
 __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename Vec<R>::V* __restrict__ v) {
   using V = typename Vec<R>::V;
   constexpr int d = 1 << K;
@@ -112,9 +116,14 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
     if (!ok[u]) continue;
     double yr[d], yi[d];
     mat_vec<K, DM>(a, xr[u], xi[u], yr, yi);
+    // (TAB 2 also keeps the row-by-row path behind a run-time test: with
+    // both paths the compiler schedules the per-coset one in fewer
+    // registers, 78 against 94 for eight rows)
+    const bool rows = TAB == 2 && a.rows;
+    if (a.nt && rows) apply_tables_rows<d>(a.tabs, a.nt, uint64_t(base[u]), yr, yi);
 #pragma unroll
     for (int r = 0; r < d; r++) {
-      if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(base[u] + a.off[r]), yr[r], yi[r]);
+      if (a.nt && !rows) apply_tables(a.tabs, a.nt, uint64_t(base[u] + a.off[r]), yr[r], yi[r]);
       v[base[u] + a.off[r]] = V{R(yr[r]), R(yi[r])};
     }
   }
@@ -263,6 +272,18 @@ bool is_diagonal_local(const LocalGate& lg) {
   return true;
 }
 
+// Per-coset header decoding pays off from this many tables (QFT-29 with
+// 3-qubit groups, up to 10 tables per operation: 94 -> 84 ms); with fewer,
+// its extra registers cost more than the scalar work it saves.
+constexpr int kRowsMinTables = 3;
+
+template <typename R, int K, bool DM>
+void launch_apply_tab(const KronArgs& a, int tab, dim3 grid, dim3 block, hipStream_t stream,
+                      typename Vec<R>::V* v) {
+  if (tab == 2) hipLaunchKernelGGL((kron_apply_kernel<R, K, DM, 2>), grid, block, 0, stream, a, v);
+  else hipLaunchKernelGGL((kron_apply_kernel<R, K, DM, 1>), grid, block, 0, stream, a, v);
+}
+
 template <typename R, bool DM>
 void dispatch_apply(const KronArgs& a, int k, bool diag, int64_t N, int num_cus, hipStream_t stream, void* v) {
   using V = typename Vec<R>::V;
@@ -274,12 +295,13 @@ void dispatch_apply(const KronArgs& a, int k, bool diag, int64_t N, int num_cus,
   }
   const int64_t blocks = (a.ncos + kBlock * kCosetsPerLane - 1) / (kBlock * kCosetsPerLane);
   const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
+  const int tab = (a.rows && a.nt >= kRowsMinTables) ? 2 : 1;
   if (k == 1)
-    hipLaunchKernelGGL((kron_apply_kernel<R, 1, DM>), grid, block, 0, stream, a, static_cast<V*>(v));
+    launch_apply_tab<R, 1, DM>(a, tab, grid, block, stream, static_cast<V*>(v));
   else if (k == 2)
-    hipLaunchKernelGGL((kron_apply_kernel<R, 2, DM>), grid, block, 0, stream, a, static_cast<V*>(v));
+    launch_apply_tab<R, 2, DM>(a, tab, grid, block, stream, static_cast<V*>(v));
   else if constexpr (!DM)
-    hipLaunchKernelGGL((kron_apply_kernel<R, 3, false>), grid, block, 0, stream, a, static_cast<V*>(v));
+    launch_apply_tab<R, 3, false>(a, tab, grid, block, stream, static_cast<V*>(v));
 }
 
 template <typename R, bool GEN, bool DM>
@@ -305,11 +327,21 @@ double kron_op_bytes(const LocalGate& core, int nf, int n, diaq_dtype_t dt) {
   return nf ? full : full / double(int64_t(1) << core.nc);
 }
 
+void kron_row_offsets(const LocalGate& lg, int64_t* off) {
+  for (int r = 0; r < (1 << lg.k); r++) {
+    int64_t o = 0;
+    for (int j = 0; j < lg.k; j++)
+      if ((r >> j) & 1) o |= int64_t(1) << lg.targets[j];
+    off[r] = o;
+  }
+}
+
 diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, int n, diaq_dtype_t dt,
-                                void* v, bool adjoint, const void* tabs, int nt, const double* dmat) {
+                                void* v, bool adjoint, const void* tabs, int nt, const double* dmat, bool rows) {
   if (dmat && lg.k > 2) return fail(DIAQ_ERR_UNSUPPORTED, "device matrices cover at most 2 targets");
   KronArgs a = make_args(lg, n, adjoint, tabs, nt);
   a.dmat = dmat;
+  a.rows = rows ? 1 : 0;
   const int64_t N = int64_t(1) << n;
   const bool diag = is_diagonal_local(lg);
   if (dt == DIAQ_C128) {

@@ -152,7 +152,7 @@ bool diagonal_factor(const diaq_gate_t* g, const LocalGate& lg, DiagFactor* f) {
 
 }  // namespace
 
-int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out) {
+int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out, const int64_t* off, int noff) {
   // group: each factor joins the table it widens least, within kTableQubits
   std::vector<uint64_t> gmask;
   std::vector<std::vector<int>> members;
@@ -190,6 +190,9 @@ int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out) {
       h.run[h.nruns++] = Q[i] | ((e - i + 1) << 8) | (i << 16);
       i = e + 1;
     }
+    for (int r = 0; r < noff && r < 8; r++)
+      for (int j = 0; j < nq; j++)
+        if ((uint64_t(off[r]) >> Q[j]) & 1) h.roff[r] |= 1 << j;
     const size_t at = out->size();
     out->resize(at + table_bytes(nq));
     std::memcpy(out->data() + at, &h, sizeof(h));
