@@ -98,11 +98,14 @@ def _basis_qft(n, j, lo, hi):
     return np.exp(1j * ph) / math.sqrt(N)
 
 
-def test_qft29_basis_state_closed_form():
+@pytest.mark.parametrize("plan", [None, dict(kron=True, fuse=True, max_fused_qubits=3)])
+def test_qft29_basis_state_closed_form(plan):
+    """Plain path, and the Alg. 3 plan with 3-qubit groups whose operations
+    carry up to ten factor tables each."""
     n, j = 29, 0x0ABCDEF3
     psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda:0")
     psi[j] = 1
-    D.apply_circuit(W.qft(n), psi)
+    D.apply_circuit(W.qft(n), psi, plan=None if plan is None else D.make_plan(**plan))
     got = to_host(psi)
     del psi
     torch.cuda.empty_cache()
