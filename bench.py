@@ -129,7 +129,17 @@ def cpu_baseline(n, gates, budget_s, bytes_of_gate):
     orc.set_threads(1)
     d1, b1, t1 = sample(max(3.0, budget_s / 3))
     orc.set_threads(cores)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "host_cpu": model, "host_cpus_visible": len(os.sched_getaffinity(0)),
             "gates_per_s": done / dt,
             "sample": "first %d of %d gates of the n=%d random layered circuit, complex128, in-place "
                       "bit-manipulation oracle (C, OpenMP); GB/s uses the same algorithmic byte model "
