@@ -242,8 +242,11 @@ diaq_status_t diaq_fuse(diaq_ctx_t ctx, diaq_dia_t first, diaq_dia_t second,
 typedef struct diaq_plan {
   int32_t fuse;             /* 1: gate-level fusion (Alg. 1 on the local
                                matrices, diagonal gates absorbed) */
-  int32_t max_fused_qubits; /* cap on a fused group's non-diagonal qubits
-                               (1..3, 0 = 2) */
+  int32_t max_fused_qubits; /* with fuse: cap on a fused group's qubits,
+                               1..3 on the DiaQ plan (non-diagonal qubits),
+                               1..5 with kron (groups of 4 or 5 qubits
+                               become dense 2^k x 2^k operations); 0 = 2;
+                               other values are INVALID_ARGUMENT */
   int32_t kron;             /* 1: Alg. 3 products, no expanded diagonals */
   int32_t rows_per_thread;  /* SpMV rows per lane (0 = tuned default) */
   int32_t block;            /* SpMV workgroup size: 0 or 256 (the kernels are
@@ -319,7 +322,7 @@ diaq_status_t diaq_expect(diaq_ctx_t ctx, diaq_dia_t H, const void* psi,
  * 3 * 2^n elements of device memory.  Writes *expval and grad[0..nparams)
  * (host, zeroed first).  plan == NULL (or kron == 0): every gate and every
  * U^dagger is expanded and applied by Alg. 2; plan->kron: the forward pass
- * runs fused Alg. 3 operations in place (max_fused_qubits, default 3) and
+ * runs fused Alg. 3 operations in place (max_fused_qubits, default 4) and
  * the reverse sweep is cut into segments of consecutive gates whose
  * non-diagonal targets fit in 3 qubits, each segment one pass over psi and
  * lambda replaying its gates per coset in exact reverse order (dots taken
