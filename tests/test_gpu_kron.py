@@ -186,20 +186,25 @@ def test_kron_staged_low_qubit_groups(S):
 def test_factor_tables_on_wave_varying_and_uniform_qubits(kmax):
     """Operations whose folded diagonal factors sit on the lowest qubits
     (which differ across a wave's cosets), on high qubits only (the same for
-    a whole wave), or on both, with plain and controlled cores: every table
-    class against the oracle, complex128 and complex64."""
-    n = 15
+    a whole wave), or on both, in one to three tables, with plain and
+    controlled cores: every table path against the oracle, complex128 and
+    complex64."""
+    n = 18
     rng = np.random.default_rng(70 + kmax)
     gates = []
-    for t in (14, 13, 12, 2, 0):
+    for t in (17, 16, 15, 2, 0):
         gates.append(W.h(t))
         for k in range(n):
             if k != t and rng.random() < 0.7:
                 gates.append(W.cp(float(rng.uniform(0, 6)), k, t))
         gates += [W.Gate("RZZ", (9, 11), (), (0.37,)), W.Gate("RZ", (1,), (), (1.1,)), W.cz(3, 10),
                   W.cp(0.2, 4, 8)]
-    gates += [W.cx(12, 14), W.cp(0.9, 1, 14), W.cp(0.4, 10, 14), W.Gate("RZZ", (9, 10), (), (0.8,)),
-              W.cx(5, 13), W.cp(1.3, 0, 13), W.cz(7, 11)]
+    # controlled cores followed by ladders over 16 other qubits (three
+    # tables): their rows with the controls off still take the factors
+    gates += [W.cx(15, 17)] + [W.cp(0.1 + 0.3 * k, k, 17) for k in range(17) if k != 15]
+    gates += [W.Gate("RZZ", (9, 10), (), (0.8,)), W.cx(5, 16), W.cp(1.3, 0, 16), W.cz(7, 11)]
+    gates += [W.Gate("RY", (11,), (3, 6), (0.7,))] + [W.cp(0.2 + 0.1 * k, k, 11) for k in range(n)
+                                                      if k not in (3, 6, 11)]
     x = W.random_state(n, 71)
     ref = orc.apply_circuit(x, n, gates)
     plan = D.make_plan(kron=True, fuse=True, max_fused_qubits=kmax)
