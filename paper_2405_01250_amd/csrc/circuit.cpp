@@ -38,18 +38,36 @@ diaq_status_t prepare_gates(const diaq_gate_t* gates, int64_t ngates, int n, Pre
 // Expand gate g into the workspace and apply it (or its adjoint) from *x
 // into *y; swaps the pointers unless the gate ran in place.
 // Packing starts in the circuit workspace: the compact diagonals one after
-// another, optionally separated by ctx->tuning.diag_pad elements so that the
+// another, each starting on a kStartAlign-byte boundary (a gate on qubit q
+// < 4 would otherwise start its later diagonals 16 2^q bytes off one, and
+// every store and load of those streams would straddle cache lines),
+// optionally separated by ctx->tuning.diag_pad more elements so that the
 // streams of one product do not sit at power-of-two distances.
-std::vector<int64_t> workspace_starts(const diaq_ctx* ctx, const std::vector<int64_t>& offs, int n) {
-  std::vector<int64_t> st = packing_starts(offs, n);
+constexpr int64_t kStartAlign = 256;
+std::vector<int64_t> workspace_starts(const diaq_ctx* ctx, const std::vector<int64_t>& offs, int n,
+                                      diaq_dtype_t dt) {
+  const std::vector<int64_t> packed = packing_starts(offs, n);
   const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
-  for (size_t k = 1; k < st.size(); k++) st[k] += int64_t(k) * pad;
+  const int64_t a = kStartAlign / int64_t(elem_bytes(dt));
+  std::vector<int64_t> st(packed.size());
+  int64_t cur = 0;
+  for (size_t k = 0; k + 1 < packed.size(); k++) {
+    st[k] = (cur + a - 1) / a * a;
+    cur = st[k] + (packed[k + 1] - packed[k]) + pad;
+  }
+  st.back() = cur;
   return st;
+}
+// Workspace elements beyond the packed values that alignment and padding
+// may add to an operation of at most kMaxArgDiags diagonals.
+int64_t workspace_slack(const diaq_ctx* ctx, diaq_dtype_t dt) {
+  const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
+  return int64_t(kMaxArgDiags + 1) * (pad + kStartAlign / int64_t(elem_bytes(dt)));
 }
 
 diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t>& offs, int n, diaq_dtype_t dt,
                    bool adjoint, void** x, void** y, const char* tabs = nullptr, int nt = 0) {
-  const std::vector<int64_t> st = workspace_starts(ctx, offs, n);
+  const std::vector<int64_t> st = workspace_starts(ctx, offs, n, dt);
   const double s = double(elem_bytes(dt));
   const double E = double(packing_starts(offs, n).back()), N = double(int64_t(1) << n);
   const size_t e0 = prof_mark(ctx);
@@ -104,8 +122,7 @@ diaq_status_t check_vectors(int n, diaq_dtype_t dt, const void* a, const void* b
 // the final state (state or scratch).
 diaq_status_t run_plain(diaq_ctx* ctx, const Prepared& p, int64_t begin, int64_t end, int n, diaq_dtype_t dt,
                         void* state, void* scratch, void** result) {
-  const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
-  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(p.max_values + (kMaxArgDiags + 1) * pad) * elem_bytes(dt)));
+  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(p.max_values + workspace_slack(ctx, dt)) * elem_bytes(dt)));
   void* x = state;
   void* y = scratch;
   for (int64_t g = begin; g < end; g++) DIAQ_TRY(step(ctx, p.lg[g], p.offs[g], n, dt, false, &x, &y));
@@ -126,8 +143,7 @@ diaq_status_t run_fused(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, d
     max_values = std::max<int64_t>(max_values, packing_starts(offs[k], n).back());
     tabs.add(ops[k].post);
   }
-  const int64_t pad = ctx->tuning.diag_pad > 0 ? ctx->tuning.diag_pad : 0;
-  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(max_values + (kMaxArgDiags + 1) * pad) * elem_bytes(dt)));
+  DIAQ_TRY(ensure(ctx, &ctx->diag, size_t(max_values + workspace_slack(ctx, dt)) * elem_bytes(dt)));
   const char* dtab = nullptr;
   if (!tabs.bytes.empty()) {
     DIAQ_TRY(ensure(ctx, &ctx->aux, tabs.bytes.size()));
