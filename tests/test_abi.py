@@ -137,3 +137,35 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def test_plan_count_host_only(lib):
+    """diaq_plan_count needs no GPU.  The plain and Alg. 3 byte models are
+    recomputed here from the definitions (a one-qubit or CX gate on target
+    t stores E = 3N - 2^(t+1) values; an Alg. 3 operation reads and writes
+    the state once, a controlled one without factors only its control-on
+    half); the fused operation counts are the planner's documented
+    figures for the n = 28 layered circuit and QFT-24."""
+    n, N, s = 28, 1 << 28, 16
+    gates = W.random_layered(n, 20, 28)
+    nops, b = D.plan_count(gates, n)
+    assert nops == 830
+    want = 0.0
+    for g in gates:
+        t = g.targets[0]
+        E = 3 * N - 2 ** (t + 1)
+        want += s * (2 * E + 2 * N)
+    assert b == pytest.approx(want, rel=1e-12)
+    nops, b = D.plan_count(gates, n, D.make_plan(kron=True))
+    assert nops == 830
+    want = sum(2 * s * N / (2 ** len(g.controls)) for g in gates)
+    assert b == pytest.approx(want, rel=1e-12)
+    counts = {(False, 2): 284, (False, 3): 154, (True, 4): 97, (True, 5): 78}
+    for (kron, k), c in counts.items():
+        assert D.plan_count(gates, n, D.make_plan(kron=kron, fuse=True, max_fused_qubits=k))[0] == c, (kron, k)
+    assert D.plan_count(W.qft(24), 24, D.make_plan(kron=True, fuse=True, max_fused_qubits=3))[0] == 20
+    for kw in (dict(fuse=True, max_fused_qubits=4), dict(kron=True, fuse=True, max_fused_qubits=6),
+               dict(fuse=True, max_fused_qubits=-1)):
+        with pytest.raises(D.DiaqError) as ei:
+            D.plan_count(gates, n, D.make_plan(**kw))
+        assert ei.value.status == 1, kw
