@@ -259,7 +259,7 @@ typedef struct diaq_plan {
  * 0 <= begin <= end <= ngates (a saved state plus a gate index resumes a
  * run).  `state` and `scratch` are distinct device vectors of 2^n
  * elements; scratch contents are clobbered.  Diagonals are expanded into
- * the context workspace. */
+ * the context workspace, each starting on a 256-byte boundary. */
 diaq_status_t diaq_apply_circuit(diaq_ctx_t ctx, const diaq_gate_t* gates,
                                  int64_t ngates, int64_t begin, int64_t end,
                                  int32_t nqubits, diaq_dtype_t dtype,
