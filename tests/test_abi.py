@@ -169,3 +169,54 @@ def test_plan_count_host_only(lib):
         with pytest.raises(D.DiaqError) as ei:
             D.plan_count(gates, n, D.make_plan(**kw))
         assert ei.value.status == 1, kw
+
+
+_ONE = ["H", "X", "Y", "Z", "S", "T", "SX", "RX", "RY", "RZ", "P", "U3"]
+_TWO = ["SWAP", "RXX", "RYY", "RZZ"]
+
+
+def _random_gate_host(rng, n):
+    """A random gate on distinct qubits: a named kind or a custom matrix of
+    1..3 targets with a random zero pattern, with up to two controls."""
+    qs = [int(q) for q in rng.permutation(n)]
+    r = rng.random()
+    if r < 0.4:
+        kind = _ONE[int(rng.integers(len(_ONE)))]
+        targets = qs[:1]
+    elif r < 0.6 and n >= 2:
+        kind = _TWO[int(rng.integers(len(_TWO)))]
+        targets = qs[:2]
+    else:
+        kind = "MATRIX"
+        k = int(rng.integers(1, min(3, n) + 1))
+        targets = qs[:k]
+    rest = qs[len(targets):]
+    nc = int(rng.integers(0, min(2, len(rest)) + 1))
+    controls = tuple(rest[:nc])
+    params = tuple(float(a) for a in rng.uniform(0.1, 6.0, 3))
+    matrix = None
+    if kind == "MATRIX":
+        d = 1 << len(targets)
+        m = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+        m[rng.random((d, d)) < 0.5] = 0
+        matrix = m
+    return W.Gate(kind, tuple(targets), controls, params, matrix=matrix)
+
+
+def test_from_gate_query_matches_brute_force_expansion(lib):
+    """The offset algebra of the expansion (host side, no GPU): for random
+    named, controlled and custom-matrix gates at n = 2..6, the offsets
+    diaq_from_gate_query reports are exactly the diagonals holding a
+    non-zero of the oracle's dense expanded matrix (plus the principal one
+    of a controlled gate, whose identity rows sit there), and the value
+    count is the sum of their lengths N - |d|."""
+    from oracle import oracle as orc
+    rng = np.random.default_rng(2024)
+    for trial in range(60):
+        n = int(rng.integers(2, 7))
+        g = _random_gate_host(rng, n)
+        offs, nv = D.from_gate_query(g, n)
+        A = orc.dense_matrix(n, [g])
+        want, _ = orc.dia_from_dense(A)
+        assert offs.tolist() == want, (trial, g)
+        assert nv == sum((1 << n) - abs(d) for d in want), trial
