@@ -74,42 +74,39 @@ void orc_apply_gate(double *psi, int n, const double *m, int k,
 }
 
 /* ------------------------------------------------------------------ */
-/* DiaQ sparse matrix-vector product, Alg. 2, run sequentially          */
+/* DiaQ sparse matrix-vector product, from the format's definition      */
 /* ------------------------------------------------------------------ */
 
 /*
- * y <- A x for a DiaQ matrix of dimension N with diagonals offsets[0..nd)
- * (dIndex = column - row).  Diagonal k holds N - |dIndex| values starting
- * at element starts[k] of vals.  The three branches are those of Alg. 2:
- * a negative diagonal's element i multiplies x[i] into y[i - dIndex], a
- * positive one's multiplies x[i + dIndex] into y[i], the principal one
- * x[i] into y[i].  No threads, so the paper's race on y cannot occur.
+ * y <- A x for a DiaQ matrix of dimension N (Sec. IV): diagonal k has
+ * index d = offsets[k] (column - row) and stores the N - |d| elements
+ * A[t + max(0,-d), t + max(0,d)], t = 0 .. N-|d|-1, from element starts[k]
+ * of vals.  So A[i, i+d] is element i - max(0,-d) of diagonal k, and
+ *
+ *     y[i] = sum over k with 0 <= i + d_k < N of  A[i, i+d_k] * x[i+d_k],
+ *
+ * taken one row at a time, diagonals in the order given.  The product is
+ * formed exactly as written, so an Inf or NaN of x reaches y[i] through
+ * every stored element of row i, zero-valued ones included.
  */
 void orc_dia_spmv(int64_t N, int nd, const int64_t *offsets,
                   const int64_t *starts, const double *vals,
                   const double *x, double *y)
 {
-    for (int64_t i = 0; i < 2 * N; i++) y[i] = 0.0;
-    for (int k = 0; k < nd; k++) {
-        const int64_t d = offsets[k];
-        const int64_t len = N - (d < 0 ? -d : d);
-        const double *v = vals + 2 * starts[k];
-        for (int64_t i = 0; i < len; i++) {
-            int64_t xi, yi;
-            if (d < 0) {
-                xi = i;
-                yi = i - d;
-            } else if (d > 0) {
-                xi = d + i;
-                yi = i;
-            } else {
-                xi = i;
-                yi = i;
-            }
-            const double vr = v[2 * i], vim = v[2 * i + 1];
-            y[2 * yi] += vr * x[2 * xi] - vim * x[2 * xi + 1];
-            y[2 * yi + 1] += vr * x[2 * xi + 1] + vim * x[2 * xi];
+    for (int64_t i = 0; i < N; i++) {
+        double ar = 0.0, ai = 0.0;
+        for (int k = 0; k < nd; k++) {
+            const int64_t d = offsets[k];
+            const int64_t j = i + d;
+            if (j < 0 || j >= N) continue;
+            const int64_t t = i - (d < 0 ? -d : 0);
+            const double vr = vals[2 * (starts[k] + t)];
+            const double vi = vals[2 * (starts[k] + t) + 1];
+            ar += vr * x[2 * j] - vi * x[2 * j + 1];
+            ai += vr * x[2 * j + 1] + vi * x[2 * j];
         }
+        y[2 * i] = ar;
+        y[2 * i + 1] = ai;
     }
 }
 

@@ -17,7 +17,8 @@ What each function follows
 * ``gate_element`` / ``dense_matrix`` / ``dia_from_dense`` -- the expanded
   time-step matrix and its DiaQ form (Sec. IV): diagonal d holds
   A[t + max(0,-d), t + max(0,d)], which is exactly numpy's ``diagonal``.
-* ``spmv_alg2`` -- Alg. 2 run sequentially (three index branches).
+* ``dia_spmv`` -- the DiaQ sparse matrix-vector product (the operation of
+  Alg. 2), written from the format's definition (Sec. IV) as a row loop.
 * ``pauli_apply`` / ``expect`` / ``energy`` -- <psi|H|phi> for a Pauli sum.
 * ``param_shift_grad`` / ``fd_grad`` -- gradients of <H> by the two-term
   parameter-shift rule and by central differences.
@@ -282,8 +283,10 @@ def pack_dia(offs, vals):
     return np.array(offs, dtype=np.int64), starts, np.ascontiguousarray(packed, dtype=np.complex128)
 
 
-def spmv_alg2(N: int, offsets, starts, values, x) -> np.ndarray:
-    """y = A x by Alg. 2 (sequential, three index branches)."""
+def dia_spmv(N: int, offsets, starts, values, x) -> np.ndarray:
+    """y = A x for a packed DiaQ matrix: y[i] = sum_k A[i, i+d_k] x[i+d_k]
+    over the diagonals k with 0 <= i + d_k < N (Sec. IV's layout gives
+    A[i, i+d] as element i - max(0,-d) of diagonal d)."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     starts = np.ascontiguousarray(starts, dtype=np.int64)
     values = np.ascontiguousarray(values, dtype=np.complex128)
@@ -326,12 +329,6 @@ def expect(n: int, terms, psi: np.ndarray, phi: np.ndarray | None = None) -> com
     if phi is None:
         phi = psi
     return inner(psi, pauli_apply(n, terms, phi))
-
-
-def expect_dense(H: np.ndarray, psi: np.ndarray, phi: np.ndarray | None = None) -> complex:
-    if phi is None:
-        phi = psi
-    return complex(np.vdot(psi, H @ phi))
 
 
 def energy(psi0: np.ndarray, n: int, gates, terms) -> float:

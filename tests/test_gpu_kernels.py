@@ -117,7 +117,7 @@ def test_spmv_random_dia(n, nd):
     x = W.random_state(n, n)
     xd = to_dev(x)
     o, s, v = orc.pack_dia(sorted(diags), [diags[d] for d in sorted(diags)])
-    ref = orc.spmv_alg2(N, o, s, v, x)
+    ref = orc.dia_spmv(N, o, s, v, x)
     scale = max(1.0, float(np.max(np.abs(ref))))
     got = to_host(D.spmv(A, xd))
     assert np.max(np.abs(got - ref)) <= 1e-13 * scale * nd

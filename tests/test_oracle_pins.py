@@ -51,7 +51,7 @@ def test_dia_worked_examples(orc, fixture):
     # The SpMV of Alg. 2 on that DiaQ matrix equals the dense product.
     o, s, v = orc.pack_dia(offs, vals)
     x = np.arange(1, 5) + 1j * np.arange(4, 0, -1)
-    assert np.allclose(orc.spmv_alg2(4, o, s, v, x), A @ x, rtol=0, atol=1e-13)
+    assert np.allclose(orc.dia_spmv(4, o, s, v, x), A @ x, rtol=0, atol=1e-13)
 
 
 def test_scipy_offsets_of_example(orc):
@@ -266,10 +266,10 @@ def test_norm_preserved_after_every_gate(orc):
 
 
 # --------------------------------------------------------------------------
-# Alg. 2 on expanded gates
+# The DiaQ SpMV (the product Alg. 2 computes) on random and expanded matrices
 # --------------------------------------------------------------------------
 
-def test_alg2_matches_dense_product(orc):
+def test_dia_spmv_matches_dense_product(orc):
     rng = np.random.default_rng(11)
     N = 64
     for nd in [1, 3, 7, 20]:
@@ -282,12 +282,41 @@ def test_alg2_matches_dense_product(orc):
         o, v = orc.dia_from_dense(A, keep_zero=True)
         o, s, v = orc.pack_dia([d for d in o if d in offs], [v[o.index(d)] for d in offs])
         x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
-        assert np.allclose(orc.spmv_alg2(N, o, s, v, x), A @ x, rtol=0, atol=1e-12)
+        assert np.allclose(orc.dia_spmv(N, o, s, v, x), A @ x, rtol=0, atol=1e-12)
 
 
-def test_ghz12_by_alg2(orc):
-    """The GHZ-12 workload run by the sequential Alg. 2 on each gate's DiaQ
-    expansion reaches the closed form."""
+def test_dia_spmv_propagates_non_finite_x(orc):
+    """Every stored element of a row multiplies its x entry, zero-valued
+    ones included (IEEE: 0 * Inf = NaN); entries that are not stored do
+    not take part.  Brute force on a 6 x 6 matrix with an explicit zero
+    diagonal: rows whose stored elements reach the Inf column are NaN, the
+    others equal the finite dense product."""
+    N = 6
+    offs = [-2, 0, 3]
+    rng = np.random.default_rng(5)
+    vals = [np.zeros(N - 2, complex), rng.standard_normal(N) + 1j * rng.standard_normal(N),
+            rng.standard_normal(N - 3) + 1j * rng.standard_normal(N - 3)]
+    o, s, v = orc.pack_dia(offs, vals)
+    for bad in (np.inf, np.nan):
+        for col in range(N):
+            x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+            x[col] = bad
+            y = orc.dia_spmv(N, o, s, v, x)
+            for i in range(N):
+                cols = [i + d for d in offs if 0 <= i + d < N]
+                if col in cols:
+                    assert not np.isfinite(y[i]), (bad, col, i)
+                else:
+                    want = 0j
+                    for d, vv in zip(offs, vals):
+                        if 0 <= i + d < N:
+                            want += vv[i - max(0, -d)] * x[i + d]
+                    assert y[i] == want, (bad, col, i)
+
+
+def test_ghz12_by_dia_spmv(orc):
+    """The GHZ-12 workload run by the oracle's DiaQ SpMV on each gate's
+    DiaQ expansion reaches the closed form."""
     n = 12
     N = 1 << n
     psi = W.zero_state(n)
@@ -301,7 +330,7 @@ def test_ghz12_by_alg2(orc):
             L = N - abs(d)
             vals.append(np.array([orc.gate_element(n, g, t + max(0, -d), t + max(0, d)) for t in range(L)]))
         o, s, v = orc.pack_dia(offs, vals)
-        psi = orc.spmv_alg2(N, o, s, v, psi)
+        psi = orc.dia_spmv(N, o, s, v, psi)
     want = np.zeros(N, dtype=complex)
     want[0] = want[-1] = 1 / math.sqrt(2)
     assert np.max(np.abs(psi - want)) <= 1e-15
@@ -526,6 +555,102 @@ def test_qaoa_p1_closed_form(orc):
             e = orc.energy(W.zero_state(n), n, gates, W.maxcut_terms(edges))
             assert abs(e - _qaoa_p1_closed_form(n, edges, gamma, beta)) < 1e-11
             assert -1e-12 <= e <= len(edges) + 1e-12
+
+
+def _closed_form_grad(n, edges, gamma, beta, h=1e-3):
+    """(dE/dgamma, dE/dbeta) of the p = 1 closed form by the five-point
+    stencil (truncation O(h^4), about 1e-12 here; rounding about 1e-12)."""
+    def d(f, t):
+        return (-f(t + 2 * h) + 8 * f(t + h) - 8 * f(t - h) + f(t - 2 * h)) / (12 * h)
+    return (d(lambda g: _qaoa_p1_closed_form(n, edges, g, beta), gamma),
+            d(lambda b: _qaoa_p1_closed_form(n, edges, gamma, b), beta))
+
+
+def test_param_shift_chain_factor_and_shared_sum_p1_closed_form(orc):
+    """QAOA p = 1: gamma drives every RZZ (angle 2 gamma) and beta every RX
+    (angle 2 beta), so each gradient entry sums |E| or n occurrences, each
+    with chain factor 2.  Both the parameter-shift gradient and the
+    theta-level central difference (angles rebuilt from theta) must equal
+    the derivative of the Wang-Hadfield-Jiang-Rieffel closed form, which is
+    independent of the oracle.  Dropping the chain factor halves the result;
+    keeping only one occurrence per slot loses all but one edge or qubit."""
+    rng = np.random.default_rng(81)
+    for n in (6, 8, 10):
+        edges = W.random_regular3(n, rng)
+        gamma, beta = rng.uniform(0, math.pi, 2)
+        terms = W.maxcut_terms(edges)
+        psi0 = W.zero_state(n)
+        gates = W.qaoa_gates(n, edges, [gamma], [beta])
+        want = np.array(_closed_form_grad(n, edges, gamma, beta))
+        ps = orc.param_shift_grad(psi0, n, gates, terms, 2)
+        assert np.max(np.abs(ps - want)) < 1e-8, (n, ps, want)
+
+        def rebuild(t):
+            return W.qaoa_gates(n, edges, [t[0]], [t[1]])
+        fd = orc.fd_grad(psi0, n, gates, terms, 2, h=1e-5, theta=[gamma, beta], rebuild=rebuild)
+        assert np.max(np.abs(fd - want)) < 1e-8, (n, fd, want)
+
+
+def test_param_shift_shared_slots_deeper_qaoa(orc):
+    """p = 2 and 3: four or six shared slots, each summed over its layer's
+    gates.  The parameter-shift gradient against the theta-level central
+    difference pinned above (h = 1e-5: the bias, h^2/6 times the third
+    derivative, and the rounding, about 1e-16 |E| / h, both stay under
+    1e-8 here)."""
+    rng = np.random.default_rng(82)
+    for n, p in ((6, 2), (8, 3)):
+        edges = W.random_regular3(n, rng)
+        gam = rng.uniform(0, math.pi, p)
+        bet = rng.uniform(0, math.pi, p)
+        terms = W.maxcut_terms(edges)
+        psi0 = W.zero_state(n)
+        gates = W.qaoa_gates(n, edges, gam, bet)
+        theta = np.empty(2 * p)
+        theta[0::2], theta[1::2] = gam, bet
+
+        def rebuild(t):
+            return W.qaoa_gates(n, edges, t[0::2], t[1::2])
+        ps = orc.param_shift_grad(psi0, n, gates, terms, 2 * p)
+        fd = orc.fd_grad(psi0, n, gates, terms, 2 * p, h=1e-5, theta=theta, rebuild=rebuild)
+        assert np.max(np.abs(ps - fd)) < 1e-7 * max(1.0, np.max(np.abs(ps))), (n, p, ps, fd)
+        assert np.max(np.abs(ps)) > 1e-2
+
+
+def test_param_shift_chain_factor_single_occurrence(orc):
+    """Rotations with chain factors s in [0.5, 2], one occurrence each:
+    E(theta_j) = c0 + c1 cos(s theta_j) + c2 sin(s theta_j), so the
+    theta-level central difference times s h / sin(s h) is the exact
+    derivative, whatever s is."""
+    n = 5
+    rng = np.random.default_rng(83)
+    kinds = ["RX", "RY", "RZ", "RXX", "RYY", "RZZ", "P"]
+    nparam = 12
+    theta = rng.uniform(0, 2 * math.pi, nparam)
+    scale = rng.uniform(0.5, 2.0, nparam)
+    layout = []
+    for j in range(nparam):
+        kind = kinds[j % len(kinds)]
+        qs = tuple(int(q) for q in rng.choice(n, 2 if kind in ("RXX", "RYY", "RZZ") else 1, replace=False))
+        layout.append((kind, qs))
+
+    prep = [W.u3(*rng.uniform(0, 2 * math.pi, 3), q) for q in range(n)]
+    post = [W.u3(*rng.uniform(0, 2 * math.pi, 3), q) for q in range(n)]
+
+    def rebuild(t):
+        gates = list(prep)
+        for j, (kind, qs) in enumerate(layout):
+            gates.append(W.Gate(kind, qs, (), (float(scale[j] * t[j]),), j, float(scale[j])))
+            gates.append(W.cx(qs[0], (qs[0] + 1) % n))
+        return gates + post
+    terms = [(0, 0b00011, 0.7), (0b00100, 0, -1.1), (0b01000, 0b01000, 0.4), (0b10001, 0b00001, 0.9)]
+    psi0 = W.zero_state(n)
+    gates = rebuild(theta)
+    ps = orc.param_shift_grad(psi0, n, gates, terms, nparam)
+    h = 1e-2
+    fd = orc.fd_grad(psi0, n, gates, terms, nparam, h=h, theta=theta, rebuild=rebuild)
+    fd *= scale * h / np.sin(scale * h)
+    assert np.max(np.abs(ps - fd)) < 1e-10, np.max(np.abs(ps - fd))
+    assert np.min(np.abs(ps)) > 1e-6
 
 
 # --------------------------------------------------------------------------
