@@ -415,6 +415,31 @@ typedef struct diaq_tuning {
 diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);
 diaq_status_t diaq_get_tuning(diaq_ctx_t ctx, diaq_tuning_t* t);
 
+/* Launch shape of the Alg. 2 product kernel for one expanded gate, as
+ * diaq_spmv and diaq_apply_circuit (plain plan) choose it under the knobs
+ * *t (NULL: built-in defaults).  Host-only: no device call, no context.
+ * Gates whose expansion holds only the principal diagonal run the in-place
+ * kernel (in_place = 1, the other fields describe one row per lane).
+ * Returns INVALID_ARGUMENT for an invalid gate or knob set. */
+typedef struct diaq_spmv_shape {
+  int32_t in_place;        /* 1: principal diagonal only, updated in place */
+  int32_t rows_per_lane;   /* rows a lane owns in each tile: 1, 2 or 4 */
+  int32_t group;           /* tiles one workgroup owns: 1, 2, 4 or 8 */
+  int32_t chunk;           /* diagonals whose loads are issued together: 1 or 3 */
+  int32_t nontemporal;     /* 1: value and y streams carry non-temporal hints */
+  int32_t tile_log2;       /* log2(rows of one tile) */
+  int32_t group_qubits[3]; /* coupling qubits the tiles of a workgroup differ
+                              in, ascending; -1 where unused */
+  int32_t xcd_run_log2;    /* > 0: each XCD takes runs of 2^xcd_run_log2
+                              consecutive tiles */
+  int32_t pair_bit;        /* > 0: each XCD alternates between tiles that
+                              differ in this tile-index bit */
+  int32_t reserved;
+  int64_t blocks;          /* workgroups of the launch */
+} diaq_spmv_shape_t;
+diaq_status_t diaq_spmv_shape(const diaq_gate_t* gate, int32_t nqubits, diaq_dtype_t dtype,
+                              const diaq_tuning_t* t, diaq_spmv_shape_t* out);
+
 /* ------------------------------------------------------------------ */
 /* Autotuning                                                           */
 /* ------------------------------------------------------------------ */

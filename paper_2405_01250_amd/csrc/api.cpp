@@ -184,6 +184,7 @@ SpmvOp op_of(const diaq_dia* A, bool transpose, bool conjugate) {
   op.transpose = transpose;
   op.conjugate = conjugate;
   op.qubit_mask = A->qubit_mask;
+  op.skip_zero = A->layout_zeros;
   return op;
 }
 
@@ -249,8 +250,7 @@ diaq_status_t diaq_synchronize(diaq_ctx_t ctx) {
   return DIAQ_OK;
 }
 
-diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t) {
-  if (!ctx || !t) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+static diaq_status_t check_tuning(const diaq_tuning_t* t) {
   if (t->spmv_rows != 0 && t->spmv_rows != 1 && t->spmv_rows != 2 && t->spmv_rows != 4)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_rows must be 0, 1, 2 or 4");
   if (t->spmv_group_bits < -1 || t->spmv_group_bits > 3)
@@ -263,8 +263,41 @@ diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t) {
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_group_min_qubit must be in [0, 63]");
   if (t->spmv_xcd_runs != 0 && t->spmv_xcd_runs != -1)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_xcd_runs must be 0 or -1");
+  return DIAQ_OK;
+}
+
+diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t) {
+  if (!ctx || !t) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+  DIAQ_TRY(check_tuning(t));
   ctx->tuning = *t;
   return DIAQ_OK;
+}
+
+diaq_status_t diaq_spmv_shape(const diaq_gate_t* gate, int32_t nqubits, diaq_dtype_t dtype, const diaq_tuning_t* t,
+                              diaq_spmv_shape_t* out) {
+  DIAQ_GUARD_BEGIN
+  if (!gate || !out) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (dtype != DIAQ_C64 && dtype != DIAQ_C128) return fail(DIAQ_ERR_INVALID_ARGUMENT, "bad dtype");
+  diaq_tuning_t tt{};
+  if (t) {
+    DIAQ_TRY(check_tuning(t));
+    tt = *t;
+  }
+  LocalGate lg;
+  DIAQ_TRY(local_gate(gate, nqubits, &lg));
+  const std::vector<int64_t> offs = gate_offsets(lg);
+  if (offs.empty()) return fail(DIAQ_ERR_INVALID_ARGUMENT, "the gate's matrix is zero");
+  const std::vector<int64_t> st = packing_starts(offs, nqubits);
+  SpmvOp op;
+  op.n = nqubits;
+  op.dtype = dtype;
+  op.nd = int(offs.size());
+  op.host_off = offs.data();
+  op.host_start = st.data();
+  op.qubit_mask = lg.tmask;
+  op.skip_zero = true;
+  return spmv_shape(op, tt, out);
+  DIAQ_GUARD_END
 }
 
 diaq_status_t diaq_get_tuning(diaq_ctx_t ctx, diaq_tuning_t* t) {
@@ -423,6 +456,7 @@ diaq_status_t diaq_from_gate(diaq_ctx_t ctx, const diaq_gate_t* gate, int32_t nq
   diaq_dia* m = nullptr;
   DIAQ_TRY(new_dia(ctx, nqubits, dtype, offs, nullptr, false, &m));
   m->qubit_mask = lg.tmask;
+  m->layout_zeros = true;
   diaq_status_t st = launch_expand(ctx, lg, nqubits, dtype, m->offsets, m->starts, m->values);
   if (st != DIAQ_OK) {
     diaq_dia_free(m);
@@ -462,6 +496,7 @@ diaq_status_t diaq_from_pauli_sum(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t 
   diaq_dia* m = nullptr;
   DIAQ_TRY(new_dia(ctx, nqubits, dtype, offs, nullptr, false, &m));
   m->qubit_mask = qmask;
+  m->layout_zeros = true;
   diaq_status_t st = launch_pauli_dia(ctx, nqubits, dtype, m->offsets, m->starts, xmask, zmask, coef, nterms,
                                       m->values);
   if (st != DIAQ_OK) {

@@ -225,6 +225,7 @@ diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype,
       op.host_start = st.data();
       op.values = ctx->diag.ptr;
       op.qubit_mask = lg.tmask;
+      op.skip_zero = true;
       for (size_t c = 0; c < cand.size(); c++) {
         ctx->tuning = cand[c];
         DIAQ_TRY(launch_spmv(ctx, op, x, y));  // warm-up
@@ -269,6 +270,8 @@ diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype,
         op.host_start = st.data();
         op.values = ctx->diag.ptr;
         op.qubit_mask = lg.tmask;
+        op.skip_zero = true;
+      op.skip_zero = true;
         double ms2[2] = {0, 0};
         for (int paired = 0; paired < 2; paired++) {
           diaq_tuning_t t = best;

@@ -90,6 +90,7 @@ diaq_status_t step(diaq_ctx* ctx, const LocalGate& lg, const std::vector<int64_t
   op.transpose = adjoint;
   op.conjugate = adjoint;
   op.qubit_mask = lg.tmask;
+  op.skip_zero = true;
   if (offs.empty()) {
     // a gate whose matrix is all zero: y = 0 (a fill kernel, no memset node
     // in a recorded graph)

@@ -131,6 +131,8 @@ struct diaq_dia {
   bool transposed = false;       // apply with negated offsets
   bool conjugated = false;       // apply with conjugated values
   uint64_t qubit_mask = 0;       // qubits whose bit the matrix may flip
+  bool layout_zeros = false;     // expanded from a gate or a Pauli sum: its zero
+                                 // values are structural, the product skips them
   int device = 0;
 };
 
@@ -355,9 +357,15 @@ struct SpmvOp {
   bool transpose = false;
   bool conjugate = false;
   uint64_t qubit_mask = 0;
+  // the matrix was expanded from a gate or a Pauli sum: its exact zeros are
+  // structural and their x loads are skipped; otherwise every stored
+  // element multiplies its x entry (a non-finite x propagates, as in Alg. 2)
+  bool skip_zero = false;
 };
 diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x,
                           void* y);
+// The launch shape launch_spmv would choose for op under the knobs t.
+diaq_status_t spmv_shape(const SpmvOp& op, const diaq_tuning_t& t, diaq_spmv_shape_t* out);
 
 // expect.hip: out2 = <psi | op | phi> reduced deterministically; result left
 // in device memory at dres (2 doubles).

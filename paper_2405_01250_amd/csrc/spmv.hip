@@ -11,9 +11,13 @@
 // Memory plan (the product is HBM-bound, ~0.3 flop/byte in fp64):
 //  * a wave reads 64 consecutive rows, so every diagonal stream and every
 //    shifted x stream is a unit-stride, 16-byte-per-lane coalesced access;
-//  * a value that is exactly zero skips its x load (expanded gates store
-//    explicit zeros on half of each off-principal diagonal, and skipping them
-//    keeps x at one HBM read per element);
+//  * on matrices expanded from a gate or a Pauli sum, a value that is
+//    exactly zero skips its x load: such zeros are structural (half of each
+//    off-principal diagonal of an expanded one-qubit gate lies outside the
+//    gate's coupling), and skipping them keeps x at one HBM read per
+//    element.  Every other matrix multiplies each stored element with its
+//    x entry, zeros included, so a non-finite x reaches y as Alg. 2 has it
+//    (0 * Inf = NaN);
 //  * offsets larger than a tile are handled by grouping tiles: one
 //    workgroup owns the tiles {base + sum s_b 2^b} for the gate's high
 //    coupling bits b, so x[i] and x[i +- 2^b] are fetched from HBM once and
@@ -93,6 +97,7 @@ struct DiagSrc {
   int32_t nd;
   int32_t transpose;
   int32_t conjugate;
+  int32_t skip_zero;     // zero values are structural: skip their x loads
 };
 
 // (applied offset e, value base vb): row i uses vals[vb + i] * x[i + e].
@@ -193,13 +198,14 @@ __device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src,
       hik[c] = e > 0 ? N - e : N;
     }
     V v[KC][ROWS];
+    bool in[KC][ROWS];
 #pragma unroll
     for (int c = 0; c < KC; c++) {
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
         const int64_t i = row[r];
-        const bool in = (i >= lok[c]) && (i < hik[c]) && (!CHECK || i < N);
-        v[c][r] = in ? ld<NT>(vals + vbk[c] + i) : V{0, 0};
+        in[c][r] = (i >= lok[c]) && (i < hik[c]) && (!CHECK || i < N);
+        v[c][r] = in[c][r] ? ld<NT>(vals + vbk[c] + i) : V{0, 0};
       }
     }
     if (src.conjugate) {
@@ -215,7 +221,7 @@ __device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src,
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
         xv[c][r] = V{0, 0};
-        if (nonzero(v[c][r])) xv[c][r] = x[row[r] + ek[c]];
+        if (in[c][r] && (!src.skip_zero || nonzero(v[c][r]))) xv[c][r] = x[row[r] + ek[c]];
       }
     // ascending diagonal order within every row
 #pragma unroll
@@ -563,6 +569,7 @@ diaq_status_t prepare(const SpmvOp& op, DiagArgs& da, DiagSrc& src) {
   src.nd = op.nd;
   src.transpose = op.transpose ? 1 : 0;
   src.conjugate = op.conjugate ? 1 : 0;
+  src.skip_zero = op.skip_zero ? 1 : 0;
   if (op.nd <= kMaxArgDiags) {
     src.dmeta = nullptr;
     da.nd = op.nd;
@@ -609,6 +616,42 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
   const Plan p = plan_rows(op, ctx->tuning, ctx->spmv_rows);
   if (op.dtype == DIAQ_C128) return launch_typed<double>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
   return launch_typed<float>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
+}
+
+diaq_status_t spmv_shape(const SpmvOp& op, const diaq_tuning_t& t, diaq_spmv_shape_t* out) {
+  std::memset(out, 0, sizeof(*out));
+  for (int b = 0; b < 3; b++) out->group_qubits[b] = -1;
+  const int64_t N = int64_t(1) << op.n;
+  if (op.nd == 1 && op.host_off[0] == 0) {
+    out->in_place = 1;
+    out->rows_per_lane = 1;
+    out->group = 1;
+    out->chunk = 1;
+    out->nontemporal = op.dtype == DIAQ_C128 ? 1 : 0;
+    out->tile_log2 = 8;
+    out->blocks = (N + kBlock - 1) / kBlock;
+    return DIAQ_OK;
+  }
+  const Plan p = plan_rows(op, t, 0);
+  // the variant launch_typed instantiates for this plan
+  out->rows_per_lane = p.rpt;
+  out->group = p.g;
+  if (op.nd > kMaxArgDiags) {
+    out->chunk = 3;
+    out->nontemporal = (!p.check && p.nt) ? 1 : 0;
+  } else if (p.g == 8) {
+    out->chunk = 1;
+    out->nontemporal = 0;
+  } else {
+    out->chunk = p.kc;
+    out->nontemporal = p.nt ? 1 : 0;
+  }
+  out->tile_log2 = p.map.tile_log2;
+  for (int b = 0; b < p.map.ng; b++) out->group_qubits[b] = p.map.gbit[b];
+  out->xcd_run_log2 = p.map.run_log2;
+  out->pair_bit = p.map.pair_bit;
+  out->blocks = p.blocks;
+  return DIAQ_OK;
 }
 
 diaq_status_t launch_final_reduce(hipStream_t stream, const double2* partial, int64_t count, double* dres) {

@@ -59,6 +59,13 @@ class diaq_tuning_t(ctypes.Structure):
                 ("spmv_xcd_runs", ctypes.c_int32), ("spmv_group_qubits", ctypes.c_uint64)]
 
 
+class diaq_spmv_shape_t(ctypes.Structure):
+    _fields_ = [("in_place", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("tile_log2", ctypes.c_int32),
+                ("group_qubits", ctypes.c_int32 * 3), ("xcd_run_log2", ctypes.c_int32),
+                ("pair_bit", ctypes.c_int32), ("reserved", ctypes.c_int32), ("blocks", ctypes.c_int64)]
+
+
 class diaq_chain_step_t(ctypes.Structure):
     _fields_ = [("ndiag", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("nvalues", ctypes.c_int64)]
@@ -105,6 +112,8 @@ _SIGS = {
                           ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(diaq_plan_t)],
     "diaq_set_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
     "diaq_get_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
+    "diaq_spmv_shape": [ctypes.POINTER(diaq_gate_t), _I32, _I32, ctypes.POINTER(diaq_tuning_t),
+                        ctypes.POINTER(diaq_spmv_shape_t)],
     "diaq_plan_count": [ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, ctypes.POINTER(diaq_plan_t),
                         ctypes.POINTER(_I64), ctypes.POINTER(_D)],
     "diaq_batch_create": [_P, _P, _I32, _U32, ctypes.POINTER(_P)],
@@ -585,13 +594,30 @@ class DiaqExpectation(torch.autograd.Function):
         th = theta.detach().cpu().double().numpy()
         gates = build(th)
         e, g = adjoint_grad(gates, H, psi0, th.size)
-        ctx.save_for_backward(torch.from_numpy(g).to(theta.dtype))
-        return torch.tensor(e, dtype=theta.dtype)
+        # the value and the saved gradient live where theta lives
+        ctx.save_for_backward(torch.from_numpy(g).to(device=theta.device, dtype=theta.dtype))
+        return torch.tensor(e, dtype=theta.dtype, device=theta.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         return grad_out * g, None, None, None
+
+
+def spmv_shape(gate, n: int, dtype=torch.complex128, **knobs) -> dict:
+    """Launch shape of the product kernel for gate's expansion at n qubits
+    under the tuning knobs (fields of diaq_tuning_t; unnamed ones 0 =
+    defaults).  Host-only, no GPU needed."""
+    t = diaq_tuning_t()
+    for k, v in knobs.items():
+        setattr(t, k, int(v))
+    keep: list = []
+    g = gate_struct(gate, keep)
+    out = diaq_spmv_shape_t()
+    _check(load().diaq_spmv_shape(ctypes.byref(g), n, _dtype_code(dtype), ctypes.byref(t), ctypes.byref(out)))
+    d = {f: getattr(out, f) for f, _ in diaq_spmv_shape_t._fields_ if f != "reserved"}
+    d["group_qubits"] = [q for q in out.group_qubits if q >= 0]
+    return d
 
 
 def plan_count(gates: Sequence, n: int, plan: diaq_plan_t | None = None, dtype=torch.complex128):

@@ -220,3 +220,48 @@ def test_from_gate_query_matches_brute_force_expansion(lib):
         want, _ = orc.dia_from_dense(A)
         assert offs.tolist() == want, (trial, g)
         assert nv == sum((1 << n) - abs(d) for d in want), trial
+
+
+def test_spmv_shape_host_only(lib):
+    """diaq_spmv_shape needs no GPU.  The knob sets of the product-variant
+    GPU tests reach every kernel shape (tile groups of 2, 4 and 8 across 1-3
+    coupling qubits, 1, 2 and 4 rows per lane, chunks of 1 and 3, streams
+    with and without non-temporal hints), workgroup counts cover the state
+    exactly once, and principal-diagonal-only gates run in place."""
+    from tests.test_gpu_spmv_variants import N_QUBITS, _DEFAULT, _GROUPINGS, _gates
+    n = N_QUBITS
+    shapes = set()
+    for g in _gates():
+        for rows in (1, 2, 4):
+            for grouping in _GROUPINGS.values():
+                for chunk in (1, 3):
+                    for nt in (0, -1):
+                        t = dict(_DEFAULT)
+                        t.update(grouping)
+                        t.update(spmv_rows=rows, spmv_chunk=chunk, spmv_nontemporal=nt)
+                        s = D.spmv_shape(g, n, **t)
+                        if s["in_place"]:
+                            assert g.kind == "RZZ"
+                            continue
+                        rows_wg = s["rows_per_lane"] * s["group"] * 256
+                        assert s["blocks"] * rows_wg == 1 << n, (g, t, s)
+                        assert s["group"] == 1 << len(s["group_qubits"])
+                        assert s["tile_log2"] == 8 + s["rows_per_lane"].bit_length() - 1
+                        assert all(q >= s["tile_log2"] for q in s["group_qubits"])
+                        shapes.add((s["rows_per_lane"], s["group"], s["chunk"], s["nontemporal"]))
+    assert {g for _, g, _, _ in shapes} == {1, 2, 4, 8}, shapes
+    assert {r for r, _, _, _ in shapes} == {1, 2, 4}, shapes
+    assert {c for _, _, c, _ in shapes} == {1, 3}, shapes
+    assert {t for _, _, _, t in shapes} == {0, 1}, shapes
+    # the defaults at n = 28: one row per lane; a U3 on qubit 27 pairs its
+    # tiles (coupling qubit >= 21); on qubit 9 the XCD runs take over
+    s = D.spmv_shape(W.u3(0.1, 0.2, 0.3, 27), 28)
+    assert (s["rows_per_lane"], s["group"], s["group_qubits"]) == (1, 2, [27])
+    s = D.spmv_shape(W.u3(0.1, 0.2, 0.3, 9), 28)
+    assert (s["group"], s["xcd_run_log2"]) == (1, 2)
+    s = D.spmv_shape(W.Gate("RZ", (5,), (), (0.3,)), 28)
+    assert s["in_place"] == 1
+    with pytest.raises(D.DiaqError):
+        D.spmv_shape(W.u3(0.1, 0.2, 0.3, 28), 28)
+    with pytest.raises(D.DiaqError):
+        D.spmv_shape(W.u3(0.1, 0.2, 0.3, 3), 28, spmv_rows=3)

@@ -188,6 +188,24 @@ def test_autograd_function():
     assert np.allclose(th.grad.numpy(), ps, atol=1e-10, rtol=0)
 
 
+def test_autograd_function_cuda_theta():
+    """theta on the GPU: E and theta.grad stay on theta's device, and the
+    gradient (through a downstream product, so grad_out is not 1) matches
+    the oracle's parameter shift."""
+    n, layers = 6, 2
+    gates, theta, terms = W.hea(n, layers, 4)
+    H = D.from_pauli_sum(n, terms)
+    psi0 = to_dev(W.zero_state(n))
+    th = torch.tensor(theta, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    E = D.DiaqExpectation.apply(th, lambda t: W.hea_gates(n, layers, t), H, psi0)
+    assert E.device == th.device
+    (3.0 * E).backward()
+    assert th.grad.device == th.device
+    ps = orc.param_shift_grad(W.zero_state(n), n, gates, terms, len(theta))
+    assert abs(float(E) - orc.energy(W.zero_state(n), n, gates, terms)) <= 1e-12
+    assert np.allclose(th.grad.cpu().numpy(), 3.0 * ps, atol=3e-10, rtol=0)
+
+
 # --------------------------------------------------------------------------
 # Gate-level fusion (plan.fuse)
 # --------------------------------------------------------------------------

@@ -17,7 +17,7 @@ from oracle import oracle as orc
 from paper_2405_01250_amd import diaq as D
 from paper_2405_01250_amd import inputs as W
 from tests.gpu_util import assert_state_close, to_dev, to_host
-from tests.test_oracle_pins import _qaoa_p1_closed_form
+from tests.test_oracle_pins import _closed_form_grad, _qaoa_p1_closed_form
 
 pytestmark = pytest.mark.gpu
 
@@ -188,3 +188,35 @@ def test_qaoa512_batch_full(graph):
         if inst.n <= 12:
             ps = orc.param_shift_grad(psi0, inst.n, inst.gates, inst.terms, 2 * inst.p)
             assert np.max(np.abs(grads[k] - ps)) <= 1e-10 * max(1.0, np.max(np.abs(ps))), k
+    if graph:
+        return
+    # gradients of the wide circuits (grouped segment passes outside the
+    # persistent kernel) against references independent of the GPU path
+    first = {}
+    for k, inst in enumerate(insts):
+        first.setdefault((inst.n, inst.p), k)
+    for n in (18, 20, 22):
+        # p = 1: the derivative of the closed form (gamma, beta)
+        k = first[(n, 1)]
+        inst = insts[k]
+        want = np.array(_closed_form_grad(inst.n, inst.edges, inst.gammas[0], inst.betas[0]))
+        assert np.max(np.abs(grads[k] - want)) <= 1e-8 * max(1.0, np.max(np.abs(want))), (k, n)
+    # p = 2 at width 18: the oracle's parameter shift, occurrence by occurrence
+    k = first[(18, 2)]
+    inst = insts[k]
+    psi0 = W.zero_state(inst.n)
+    ps = orc.param_shift_grad(psi0, inst.n, inst.gates, inst.terms, 2 * inst.p)
+    assert np.max(np.abs(grads[k] - ps)) <= 1e-10 * max(1.0, np.max(np.abs(ps))), k
+    # p >= 2 at widths 20 and 22: the oracle's central differences on the
+    # angles (h = 1e-5; shared angles move together)
+    for n, pp in ((20, 4), (22, 2)):
+        k = first[(n, pp)]
+        inst = insts[k]
+        theta0 = np.ravel(np.column_stack([inst.gammas, inst.betas]))
+
+        def rebuild(t, inst=inst):
+            return W.qaoa_gates(inst.n, inst.edges, t[0::2], t[1::2])
+
+        fd = orc.fd_grad(W.zero_state(inst.n), inst.n, None, inst.terms, 2 * inst.p, h=1e-5, theta=theta0,
+                         rebuild=rebuild)
+        assert np.linalg.norm(grads[k] - fd) <= 1e-6 * np.linalg.norm(fd), (k, n)

@@ -101,7 +101,7 @@ def _random_dia(rng, n, nd):
     for d in offs:
         L = N - abs(d)
         v = rng.standard_normal(L) + 1j * rng.standard_normal(L)
-        v[rng.random(L) < 0.2] = 0  # explicit zeros exercise the zero skip
+        v[rng.random(L) < 0.2] = 0  # explicit zeros: stored elements like any other
         diags[d] = v
     return diags
 
@@ -150,6 +150,76 @@ def test_spmv_gates_match_oracle(n):
         # adjoint undoes the gate
         back = to_host(D.spmv(A, to_dev(got), flags=D.ADJOINT))
         assert_state_close(back, x, TOL64, "adjoint " + str(g))
+
+
+def _classes(y):
+    """Per component: 0 finite, 1 NaN, 2 +Inf, 3 -Inf."""
+    out = []
+    for c in (y.real, y.imag):
+        k = np.zeros(c.shape, np.int8)
+        k[np.isnan(c)] = 1
+        k[np.isposinf(c)] = 2
+        k[np.isneginf(c)] = 3
+        out.append(k)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("bad", [np.inf, np.nan, complex(0, -np.inf)])
+def test_spmv_caller_matrix_propagates_non_finite_x(bad):
+    """A caller-built matrix multiplies every stored element with its x entry,
+    explicit zeros included (Alg. 2; 0 * Inf = NaN): the non-finite pattern of
+    y and its finite values match the oracle's product, in both dtypes' fp64
+    case, also through the transposed view."""
+    rng = np.random.default_rng(31)
+    n = 10
+    N = 1 << n
+    diags = {}
+    for d in (-300, -3, 0, 5, 257):
+        L = N - abs(d)
+        diags[d] = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    diags[5][:] = 0          # an explicit all-zero diagonal
+    diags[-3][::7] = 0       # scattered explicit zeros
+    A = D.from_dense_diagonals(n, diags)
+    x = W.random_state(n, 8)
+    for col in (0, 37, 518, N - 1):
+        x[col] = bad
+    o, s_, v = orc.pack_dia(sorted(diags), [diags[d] for d in sorted(diags)])
+    ref = orc.dia_spmv(N, o, s_, v, x)
+    got = to_host(D.spmv(A, to_dev(x)))
+    assert (_classes(got) == _classes(ref)).all()
+    fin = np.isfinite(ref)
+    assert (~fin).any() and fin.any()
+    assert np.max(np.abs(got[fin] - ref[fin])) <= 1e-13
+    # the transposed view: A^T's stored elements are A's, so the oracle's
+    # product on the relabelled diagonals
+    tdiags = {-d: vv for d, vv in diags.items()}
+    o, s_, v = orc.pack_dia(sorted(tdiags), [tdiags[d] for d in sorted(tdiags)])
+    ref_t = orc.dia_spmv(N, o, s_, v, x)
+    got_t = to_host(D.spmv(A, to_dev(x), flags=D.TRANSPOSE))
+    assert (_classes(got_t) == _classes(ref_t)).all()
+    fin = np.isfinite(ref_t)
+    assert np.max(np.abs(got_t[fin] - ref_t[fin])) <= 1e-13
+
+
+def test_spmv_expanded_gate_skips_structural_zeros():
+    """A gate's expansion stores structural zeros (a diagonal +-2^q of a
+    one-qubit gate is zero on the rows outside the gate's coupling); the
+    product skips them, so a non-finite x entry reaches exactly the rows whose
+    time-step matrix has a non-zero in its column, and every other row equals
+    the product over the non-zero entries."""
+    n = 10
+    N = 1 << n
+    x = W.random_state(n, 9)
+    col = 300
+    x[col] = np.inf
+    xf = x.copy()
+    xf[col] = 0
+    for g in [W.u3(0.3, 1.1, 2.2, 3), W.cx(2, 7), W.swap(1, 8), W.Gate("RXX", (0, 9), (), (0.4,))]:
+        Ad = orc.dense_matrix(n, [g])
+        got = to_host(D.spmv(D.from_gate(g, n), to_dev(x)))
+        hit = Ad[:, col] != 0
+        assert not np.isfinite(got[hit]).any(), g
+        assert np.max(np.abs(got[~hit] - (Ad @ xf)[~hit])) <= 1e-13, g
 
 
 def test_spmv_complex64():

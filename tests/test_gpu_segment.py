@@ -116,3 +116,27 @@ def test_segmented_hea_and_qaoa(n, layers):
     e_k, g_k = D.adjoint_grad(qg, C, psi0, 4, plan=D.make_plan(kron=True))
     e_p, g_p = D.adjoint_grad(qg, C, psi0, 4)
     assert abs(e_k - e_p) <= 1e-11 and np.max(np.abs(g_k - g_p)) <= 1e-10
+    # the segmented sweep against the oracle itself
+    x0 = W.zero_state(n)
+    cterms = W.maxcut_terms(edges)
+    e_o = orc.energy(x0, n, qg, cterms)
+    assert abs(e_k - e_o) <= 1e-11 * max(1.0, abs(e_o))
+    if n <= 16:
+        ps = orc.param_shift_grad(x0, n, qg, cterms, 4)
+        assert np.max(np.abs(g_k - ps)) <= 1e-10 * max(1.0, np.max(np.abs(ps)))
+    else:
+        th0 = np.ravel(np.column_stack([gam, bet]))
+        fd = orc.fd_grad(x0, n, None, cterms, 4, h=1e-5, theta=th0,
+                         rebuild=lambda t: W.qaoa_gates(n, edges, t[0::2], t[1::2]))
+        assert np.linalg.norm(g_k - fd) <= 1e-6 * np.linalg.norm(fd)
+    # sampled HEA entries against the oracle's parameter shift (one
+    # occurrence per parameter)
+    gates, theta, terms = W.hea(n, layers, 60 + n)
+    g_h = D.adjoint_grad(gates, H, psi0, len(theta), plan=D.make_plan(kron=True))[1]
+    for j in (0, len(theta) // 2, len(theta) - 1):
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += math.pi / 2
+        tm[j] -= math.pi / 2
+        ps = 0.5 * (orc.energy(x0, n, W.hea_gates(n, layers, tp), terms)
+                    - orc.energy(x0, n, W.hea_gates(n, layers, tm), terms))
+        assert abs(g_h[j] - ps) <= 1e-10 * max(1.0, abs(ps)), (n, j)
