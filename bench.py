@@ -47,7 +47,11 @@ def _args():
                     help="JSON file of autotuned product-kernel knobs (read if it holds this size, else written)")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy", "sweep"],
                     help="copy: run a plain device copy of 2^n complex elements (counter calibration); "
-                         "sweep: single-gate expansion + SpMV rates per target qubit (one JSON line per gate)")
+                         "sweep: single-gate rates per target qubit (one JSON line per gate)")
+    ap.add_argument("--sweep-plan", default="dia", choices=["dia", "kron", "groups"],
+                    help="sweep: dia = expansion + DiaQ SpMV per gate; kron = Alg. 3 in-place product per "
+                         "gate; groups = Alg. 3 fused dense groups of 3, 4 and 5 consecutive qubits")
+    ap.add_argument("--sweep-dtypes", default="c128,c64", help="sweep: dtypes to run")
     return ap.parse_args()
 
 
@@ -101,34 +105,57 @@ def _traffic_from_profiles(kernel_src: str):
         return None
 
 
-def cpu_baseline(n, gates, budget_s, bytes_of_gate):
-    """The CPU oracle, as it stands, on the first gates of the same circuit
-    until the time budget is spent: on every host core, then (a third of
-    the budget) on one."""
+def cpu_baseline(n, gates, budget_s, s_bytes, repeats=3):
+    """The CPU oracle, as it stands, on the first gates of the same circuit:
+    `repeats` bounded samples on every host core, then on one core.  GB/s
+    follows the oracle's own byte model: it applies each gate in place,
+    reading and writing the 2^n-element state once (2 N s bytes per gate).
+    Also the oracle's parameter-shift gradient of the HEA n = 20 workload,
+    timed on a few of its 640 shifted energies."""
+    import numpy as np
+
     from oracle import oracle as orc
     from paper_2405_01250_amd import inputs as W
 
     orc.build()
+    per_gate = 2.0 * (1 << n) * s_bytes
 
     def sample(budget):
         psi = W.zero_state(n)
-        done, nbytes = 0, 0.0
+        done = 0
         t0 = time.perf_counter()
         for g in gates:
             orc.apply_gate(psi, n, g)
             done += 1
-            nbytes += bytes_of_gate(g)
             if time.perf_counter() - t0 >= budget:
                 break
-        return done, nbytes, time.perf_counter() - t0
+        return done, time.perf_counter() - t0
+
+    def stats(runs):
+        rates = np.array([d / t for d, t in runs])
+        return {"value": round(float(rates.mean()) * per_gate / 1e9, 2),
+                "std": round(float(rates.std()) * per_gate / 1e9, 2), "unit": "GB/s",
+                "gates_per_s": round(float(rates.mean()), 3), "gates_per_s_std": round(float(rates.std()), 3),
+                "runs": [{"gates": d, "s": round(t, 3)} for d, t in runs]}
 
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     orc.set_threads(cores)
     cores = orc.get_threads()
-    done, nbytes, dt = sample(budget_s)
+    sample(1.0)  # warm-up: pages the state in
+    all_cores = stats([sample(budget_s / repeats) for _ in range(repeats)])
     orc.set_threads(1)
-    d1, b1, t1 = sample(max(3.0, budget_s / 3))
+    one = stats([sample(max(1.0, budget_s / (3 * repeats))) for _ in range(repeats)])
     orc.set_threads(cores)
+    # gradient baseline: parameter shift needs 2 energies per occurrence
+    hn, layers = 20, 8
+    hg, theta, terms = W.hea(hn, layers, 20)
+    x0 = W.zero_state(hn)
+    t0 = time.perf_counter()
+    k = 0
+    while k < 4:
+        orc.energy(x0, hn, hg, terms)
+        k += 1
+    e_s = (time.perf_counter() - t0) / k
     model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -138,20 +165,40 @@ def cpu_baseline(n, gates, budget_s, bytes_of_gate):
                     break
     except OSError:
         pass
-    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
-            "host_cpu": model, "host_cpus_visible": len(os.sched_getaffinity(0)),
-            "gates_per_s": done / dt,
-            "sample": "first %d of %d gates of the n=%d random layered circuit, complex128, in-place "
-                      "bit-manipulation oracle (C, OpenMP); GB/s uses the same algorithmic byte model "
-                      "as value" % (done, len(gates), n),
-            "one_core": {"value": b1 / t1 / 1e9, "unit": "GB/s", "gates_per_s": d1 / t1,
-                         "sample": "first %d gates, same circuit, one thread" % d1}}
+    out = dict(all_cores)
+    out.update({"cores": cores, "kind": "oracle", "host_cpu": model,
+                "host_cpus_visible": len(os.sched_getaffinity(0)),
+                "sample": "%d runs of about %.0f s each: the first gates of the n=%d random layered circuit "
+                          "from |0..0>, complex128, in-place bit-manipulation oracle (C, OpenMP); GB/s = "
+                          "gates/s x 2 N s (the oracle's in-place read + write of the state); mean and std over "
+                          "the runs" % (repeats, budget_s / repeats, n),
+                "one_core": one,
+                "hea20_param_shift": {"energy_s": round(e_s, 3), "shifted_energies": 2 * len(theta),
+                                      "grads_per_s": round(1.0 / (2 * len(theta) * e_s), 5),
+                                      "sample": "%d energies of the HEA n=20 circuit (480 gates) timed on all "
+                                                "cores; a full gradient takes 2 x %d of them" % (k, len(theta))}})
+    return out
+
+
+def _group_circuit(W, rng, qs):
+    """Gates that the Alg. 3 planner fuses into one dense operation on the
+    qubits qs: a CX chain along them (which opens one operation over all of
+    them), a U3 on each, the chain again and a U3 on each again."""
+    gates = []
+    for _ in range(2):
+        gates += [W.cx(qs[j], qs[j + 1]) for j in range(len(qs) - 1)]
+        gates += [W.u3(*rng.uniform(0, 2 * math.pi, 3), q) for q in qs]
+    return gates
 
 
 def sweep_mode(a):
-    """Single-gate sweep at 2^n amplitudes: for each gate shape and target
-    qubit, expansion and SpMV rates from HIP events (algorithmic bytes:
-    s*E written by the expansion, s*(E + 2N) moved by the product)."""
+    """Single-operation sweep at 2^n amplitudes, rates from HIP events around
+    every launch.  dia: each gate shape on each target qubit, expanded and
+    applied by the DiaQ SpMV (algorithmic bytes s*E written by the expansion,
+    s*(E + 2N) moved by the product).  kron: the same gates by Alg. 3 in
+    place (2 s N per gate, 2 s N / 2 for a controlled one).  groups: one
+    fused dense Alg. 3 operation on k = 3, 4, 5 consecutive qubits starting
+    at each position (2 s N)."""
     import numpy as np
     import torch
 
@@ -161,30 +208,45 @@ def sweep_mode(a):
     n = a.n
     rng = np.random.default_rng(a.seed)
     ctx = D.context()
-    for dt_name, tdt in (("c128", torch.complex128), ("c64", torch.complex64)):
+    dts = {"c128": torch.complex128, "c64": torch.complex64}
+    for dt_name in a.sweep_dtypes.split(","):
+        tdt = dts[dt_name]
         psi = torch.from_numpy(W.random_state(n, a.seed)).to("cuda:0").to(tdt)
         scratch = torch.empty_like(psi)
-        D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
-        shapes = [("U3", lambda q: W.u3(*rng.uniform(0, 2 * math.pi, 3), q)),
-                  ("CX", lambda q: W.cx(0, q) if q else W.cx(1, 0)),
-                  ("RZ", lambda q: W.Gate("RZ", (q,), (), (0.7,))),
-                  ("CZ", lambda q: W.Gate("Z", (q,), (0 if q else 1,))),
-                  ("SWAP", lambda q: W.swap(q, n - 1 - q) if q != n - 1 - q else W.swap(q, 0))]
-        for name, make in shapes:
-            for q in range(n):
-                g = [make(q)]
-                arr = D.gate_array(g)
-                D.apply_circuit(g, psi, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
-                torch.cuda.synchronize()
-                D.profile_start(ctx)
-                for _ in range(a.steps):
-                    D.apply_circuit(g, psi, n=n, scratch=scratch, marshalled=arr, ctx=ctx)
-                p = D.profile_stop(ctx)
-                out = {"mode": "sweep", "dtype": dt_name, "n": n, "gate": name, "q": q,
-                       "spmv_us": round(p["spmv_ms"] / max(1, p["spmv_launches"]) * 1e3, 1),
-                       "spmv_GBps": round(p["spmv_bytes"] / p["spmv_ms"] / 1e6, 1) if p["spmv_ms"] else None,
-                       "expand_GBps": round(p["expand_bytes"] / p["expand_ms"] / 1e6, 1) if p["expand_ms"] else None}
-                print(json.dumps(out), flush=True)
+        tuning = D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
+        print(json.dumps({"mode": "sweep", "dtype": dt_name, "n": n, "plan": a.sweep_plan, "tuning": tuning}),
+              flush=True)
+        cases = []
+        if a.sweep_plan in ("dia", "kron"):
+            shapes = [("U3", lambda q: W.u3(*rng.uniform(0, 2 * math.pi, 3), q)),
+                      ("CX", lambda q: W.cx(0, q) if q else W.cx(1, 0)),
+                      ("RZ", lambda q: W.Gate("RZ", (q,), (), (0.7,))),
+                      ("CZ", lambda q: W.Gate("Z", (q,), (0 if q else 1,))),
+                      ("SWAP", lambda q: W.swap(q, n - 1 - q) if q != n - 1 - q else W.swap(q, 0))]
+            plan = D.make_plan(kron=True) if a.sweep_plan == "kron" else None
+            for name, make in shapes:
+                for q in range(n):
+                    cases.append((name, q, [make(q)], plan))
+        else:
+            for k in (3, 4, 5):
+                plan = D.make_plan(kron=True, fuse=True, max_fused_qubits=k)
+                for q in range(n - k + 1):
+                    gates = _group_circuit(W, rng, list(range(q, q + k)))
+                    assert D.plan_count(gates, n, plan, dtype=tdt)[0] == 1
+                    cases.append(("G%d" % k, q, gates, plan))
+        for name, q, g, plan in cases:
+            arr = D.gate_array(g)
+            D.apply_circuit(g, psi, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+            torch.cuda.synchronize()
+            D.profile_start(ctx)
+            for _ in range(a.steps):
+                D.apply_circuit(g, psi, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+            p = D.profile_stop(ctx)
+            out = {"mode": "sweep", "plan": a.sweep_plan, "dtype": dt_name, "n": n, "gate": name, "q": q,
+                   "spmv_us": round(p["spmv_ms"] / max(1, p["spmv_launches"]) * 1e3, 1),
+                   "spmv_GBps": round(p["spmv_bytes"] / p["spmv_ms"] / 1e6, 1) if p["spmv_ms"] else None,
+                   "expand_GBps": round(p["expand_bytes"] / p["expand_ms"] / 1e6, 1) if p["expand_ms"] else None}
+            print(json.dumps(out), flush=True)
         del psi, scratch
         torch.cuda.empty_cache()
 
@@ -323,8 +385,7 @@ def main():
     if a.cpu_seconds > 0:
         del state, scratch, Hzz
         torch.cuda.empty_cache()
-        eb = {id(g): s * e + s * (e + 2 * N) for g, e in zip(gates, E)}
-        out["cpu_baseline"] = cpu_baseline(n, gates, a.cpu_seconds, lambda g: eb[id(g)])
+        out["cpu_baseline"] = cpu_baseline(n, gates, a.cpu_seconds, s)
     print(json.dumps(out), flush=True)
 
 
@@ -346,10 +407,17 @@ def fused_extra(D, gates, state, scratch, ctx, n, steps, **kw):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = D.profile_stop(ctx)
+    pg = prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9 if prof["spmv_ms"] else None
+    if kw.get("kron"):
+        kern = ("kron_big_kernel / kron_lds_kernel (Alg. 3, dense groups of up to %d qubits)" % kmax
+                if kmax > 3 else "kron_apply_kernel / kron_lds_kernel / kron_diag_kernel (Alg. 3)")
+    else:
+        kern = "spmv_kernel (DiaQ SpMV, Alg. 2)"
     return {"plan": ("kron" if kw.get("kron") else "dia") + ("+fuse%d" % kmax if kw.get("fuse") else ""),
             "ops": nops, "gates": len(gates), "ms_per_step": round(dt / steps * 1e3, 3),
             "gates_per_s": round(len(gates) * steps / dt, 2), "GBps": round(nbytes * steps / dt / 1e9, 1),
-            "product_GBps": round(prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9, 1) if prof["spmv_ms"] else None,
+            "product_GBps": round(pg, 1) if pg else None,
+            "product_frac": round(pg / HBM_PEAK_GBPS, 4) if pg else None, "product_kernel": kern,
             "expand_GBps": round(prof["expand_bytes"] / (prof["expand_ms"] * 1e-3) / 1e9, 1)
             if prof["expand_ms"] else None}
 

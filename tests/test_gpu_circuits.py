@@ -202,7 +202,7 @@ def test_autograd_function_cuda_theta():
     (3.0 * E).backward()
     assert th.grad.device == th.device
     ps = orc.param_shift_grad(W.zero_state(n), n, gates, terms, len(theta))
-    assert abs(float(E) - orc.energy(W.zero_state(n), n, gates, terms)) <= 1e-12
+    assert abs(float(E.detach()) - orc.energy(W.zero_state(n), n, gates, terms)) <= 1e-12
     assert np.allclose(th.grad.cpu().numpy(), 3.0 * ps, atol=3e-10, rtol=0)
 
 
