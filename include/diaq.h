@@ -314,6 +314,24 @@ diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates,
 diaq_status_t diaq_expect(diaq_ctx_t ctx, diaq_dia_t H, const void* psi,
                           const void* phi, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * expectation value of diaq_expect, same kernels and summation order, with
+ * no allocation, no free and no synchronisation.  The result (real part,
+ * imaginary part) is written to dres, caller-owned device memory of two
+ * doubles, asynchronously on the context's stream.  psi, phi (NULL: psi)
+ * and dres are 16-byte aligned.  The per-workgroup partial sums live in a
+ * static device array of 2^20 entries (16 MiB) that each device the
+ * library runs on holds until the process ends; a matrix whose product
+ * needs more partials than that (more than 2^28 rows at the default one row
+ * per lane) returns DIAQ_ERR_UNSUPPORTED before anything is launched.
+ * Every partial is written before it is read, so nothing carries over from
+ * an earlier call, but all calls on one device share the array: calls that
+ * overlap in time (other streams, other contexts, other host threads) race
+ * and must be serialised by the caller. */
+diaq_status_t diaq_expect_noalloc(diaq_ctx_t ctx, diaq_dia_t H, const void* psi,
+                                  const void* phi, double* dres);
+
 /* Adjoint gradient of E(theta) = <psi|H|psi>, psi = U_G...U_1 psi0.
  * Forward pass, lambda = H psi, then a reverse sweep that for g = G..1
  * adds param_scale * Im<lambda|G_g|psi> to grad[param_index] of every

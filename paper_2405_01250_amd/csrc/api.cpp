@@ -226,6 +226,8 @@ diaq_status_t diaq_create(int32_t device, void* hip_stream, diaq_ctx_t* out) {
   if (device < 0 || device >= count)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "device %d not in [0, %d)", device, count);
   DIAQ_HIP(hipSetDevice(device));
+  // the device address of the static scratch array, once per device
+  DIAQ_TRY(init_static_scratch(device));
   diaq_ctx* c = new diaq_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -551,6 +553,15 @@ diaq_status_t diaq_expect(diaq_ctx_t ctx, diaq_dia_t H, const void* psi, const v
   out[0] = ctx->pinned[0];
   out[1] = ctx->pinned[1];
   return DIAQ_OK;
+  DIAQ_GUARD_END
+}
+
+diaq_status_t diaq_expect_noalloc(diaq_ctx_t ctx, diaq_dia_t H, const void* psi, const void* phi, double* dres) {
+  DIAQ_GUARD_BEGIN
+  if (!ctx || !H || !psi || !dres) return fail(DIAQ_ERR_INVALID_ARGUMENT, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(psi) | reinterpret_cast<uintptr_t>(phi) | reinterpret_cast<uintptr_t>(dres)) & 15)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "psi, phi and dres must be 16-byte aligned");
+  return launch_expect_static(ctx, op_of(H, H->transposed, H->conjugated), psi, phi ? phi : psi, dres);
   DIAQ_GUARD_END
 }
 

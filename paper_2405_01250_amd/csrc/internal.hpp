@@ -371,6 +371,16 @@ diaq_status_t spmv_shape(const SpmvOp& op, const diaq_tuning_t& t, diaq_spmv_sha
 // in device memory at dres (2 doubles).
 diaq_status_t launch_expect(diaq_ctx* ctx, const SpmvOp& op, const void* psi,
                             const void* phi, double* dres);
+// The same product and reduction with its partial sums in the library's
+// static device array (kStaticPartials entries per device) instead of a
+// context workspace: allocates nothing; products that need more partials
+// return DIAQ_ERR_UNSUPPORTED.  init_static_scratch(device), called with
+// that device current (diaq_create), takes the array's device address.
+constexpr int64_t kStaticPartials = int64_t(1) << 20;
+constexpr int kMaxStaticDevices = 64;
+diaq_status_t init_static_scratch(int device);
+diaq_status_t launch_expect_static(diaq_ctx* ctx, const SpmvOp& op, const void* psi,
+                                   const void* phi, double* dres);
 // <lam | G | psi> for a local generator applied by index bit manipulation.
 diaq_status_t launch_generator_dot(diaq_ctx* ctx, const LocalGate& gen, int n,
                                    diaq_dtype_t dt, const void* lam,

@@ -23,7 +23,17 @@
 //    coupling bits b, so x[i] and x[i +- 2^b] are fetched from HBM once and
 //    re-read from L1/L2 of the same CU (workgroups are spread round-robin
 //    over the 8 XCDs, so sharing across workgroups would not hit one L2).
+#include <mutex>
+
 #include "internal.hpp"
+
+// Per-workgroup partial sums of the allocation-free expectation
+// (diaq_expect_noalloc): kStaticPartials entries, 16 MiB, enough for the
+// product of a 2^28-row matrix at one row per lane.  Each device holds its
+// own copy until the process ends.  In host code this name is only a
+// host-side stand-in: kernels receive the device address that
+// init_static_scratch takes with hipGetSymbolAddress.
+static __device__ __align__(256) double2 scratch[diaq::kStaticPartials];
 
 namespace diaq {
 
@@ -676,6 +686,48 @@ diaq_status_t launch_expect(diaq_ctx* ctx, const SpmvOp& op, const void* psi, co
   const Plan p = plan_rows(op, ctx->tuning, ctx->spmv_rows);
   DIAQ_TRY(ensure(ctx, &ctx->red, size_t(p.blocks) * sizeof(double2)));
   double2* partial = static_cast<double2*>(ctx->red.ptr);
+  if (op.dtype == DIAQ_C128)
+    DIAQ_TRY(launch_typed<double>(ctx, op, da, src, p, op.values, phi, nullptr, partial, psi));
+  else
+    DIAQ_TRY(launch_typed<float>(ctx, op, da, src, p, op.values, phi, nullptr, partial, psi));
+  return final_reduce(ctx, partial, p.blocks, dres);
+}
+
+namespace {
+std::mutex g_static_mu;
+double2* g_static_ptr[kMaxStaticDevices] = {};
+}  // namespace
+
+diaq_status_t init_static_scratch(int device) {
+  if (device < 0 || device >= kMaxStaticDevices)
+    return fail(DIAQ_ERR_UNSUPPORTED, "device %d beyond the %d devices of the static scratch table", device,
+                kMaxStaticDevices);
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (g_static_ptr[device]) return DIAQ_OK;
+  void* ptr = nullptr;
+  DIAQ_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(DIAQ_ERR_DEVICE, "no device address for the static scratch of device %d", device);
+  g_static_ptr[device] = static_cast<double2*>(ptr);
+  return DIAQ_OK;
+}
+
+diaq_status_t launch_expect_static(diaq_ctx* ctx, const SpmvOp& op, const void* psi, const void* phi, double* dres) {
+  double2* partial = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (ctx->device >= 0 && ctx->device < kMaxStaticDevices) partial = g_static_ptr[ctx->device];
+  }
+  if (!partial) return fail(DIAQ_ERR_DEVICE, "static scratch of device %d was not set up", ctx->device);
+  // a matrix without diagonals: <psi|0|phi> = 0 by a fill kernel
+  if (op.nd == 0) return launch_zero(ctx->stream, dres, 2 * sizeof(double));
+  DiagArgs da;
+  DiagSrc src;
+  DIAQ_TRY(prepare(op, da, src));
+  const Plan p = plan_rows(op, ctx->tuning, ctx->spmv_rows);
+  if (p.blocks > kStaticPartials)
+    return fail(DIAQ_ERR_UNSUPPORTED, "the product needs %lld partial sums, the static scratch holds %lld",
+                (long long)p.blocks, (long long)kStaticPartials);
+  // every workgroup writes its own partial, so nothing needs clearing
   if (op.dtype == DIAQ_C128)
     DIAQ_TRY(launch_typed<double>(ctx, op, da, src, p, op.values, phi, nullptr, partial, psi));
   else

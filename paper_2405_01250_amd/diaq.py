@@ -108,6 +108,7 @@ _SIGS = {
     "diaq_apply_circuit": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I64, _I64, _I32, _I32, _P, _P,
                            ctypes.POINTER(diaq_plan_t)],
     "diaq_expect": [_P, _P, _P, _P, ctypes.POINTER(_D)],
+    "diaq_expect_noalloc": [_P, _P, _P, _P, _P],
     "diaq_adjoint_grad": [_P, ctypes.POINTER(diaq_gate_t), _I64, _I32, _I32, _P, _P, _P, _I64,
                           ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(diaq_plan_t)],
     "diaq_set_tuning": [_P, ctypes.POINTER(diaq_tuning_t)],
@@ -528,6 +529,18 @@ def expect(H: DiaqMatrix, psi: torch.Tensor, phi: torch.Tensor | None = None) ->
     _check(load().diaq_expect(H.ctx.handle, H.handle, _vec(psi, n, dt, "psi"),
                               _vec(phi, n, dt, "phi") if phi is not None else None, out))
     return complex(out[0], out[1])
+
+
+def expect_noalloc(H: DiaqMatrix, psi: torch.Tensor, out: torch.Tensor, phi: torch.Tensor | None = None) -> torch.Tensor:
+    """<psi|H|phi> written into out (float64 device tensor of 2 elements:
+    real, imaginary) without any allocation or synchronisation (for graph
+    capture and serving loops); returns out."""
+    n, _, dt, _, _ = H.info()
+    if out.dtype != torch.float64 or out.numel() < 2 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 device tensor of 2 elements")
+    _check(load().diaq_expect_noalloc(H.ctx.handle, H.handle, _vec(psi, n, dt, "psi"),
+                                      _vec(phi, n, dt, "phi") if phi is not None else None, _P(out.data_ptr())))
+    return out
 
 
 def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: int,
