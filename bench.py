@@ -52,6 +52,8 @@ def _args():
                     help="sweep: dia = expansion + DiaQ SpMV per gate; kron = Alg. 3 in-place product per "
                          "gate; groups = Alg. 3 fused dense groups of 3, 4 and 5 consecutive qubits")
     ap.add_argument("--sweep-dtypes", default="c128,c64", help="sweep: dtypes to run")
+    ap.add_argument("--knobs", default="", help="JSON object of tuning knobs set after autotuning "
+                                                "(fields of diaq_tuning_t), e.g. '{\"kron_split\": 2}'")
     return ap.parse_args()
 
 
@@ -213,13 +215,17 @@ def sweep_mode(a):
         tdt = dts[dt_name]
         psi = torch.from_numpy(W.random_state(n, a.seed)).to("cuda:0").to(tdt)
         scratch = torch.empty_like(psi)
-        tuning = D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
+        D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
+        if a.knobs:
+            D.set_tuning(ctx, **json.loads(a.knobs))
+        tuning = D.get_tuning(ctx)
         print(json.dumps({"mode": "sweep", "dtype": dt_name, "n": n, "plan": a.sweep_plan, "tuning": tuning}),
               flush=True)
         cases = []
         if a.sweep_plan in ("dia", "kron"):
             shapes = [("U3", lambda q: W.u3(*rng.uniform(0, 2 * math.pi, 3), q)),
                       ("CX", lambda q: W.cx(0, q) if q else W.cx(1, 0)),
+                      ("CXhi", lambda q: W.cx(n - 1 if q != n - 1 else n - 2, q)),
                       ("RZ", lambda q: W.Gate("RZ", (q,), (), (0.7,))),
                       ("CZ", lambda q: W.Gate("Z", (q,), (0 if q else 1,))),
                       ("SWAP", lambda q: W.swap(q, n - 1 - q) if q != n - 1 - q else W.swap(q, 0))]
@@ -301,6 +307,9 @@ def main():
 
     # product-kernel knobs chosen by the autotuner at this size (untimed)
     tuning = D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
+    if a.knobs:
+        D.set_tuning(ctx, **json.loads(a.knobs))
+        tuning = D.get_tuning(ctx)
 
     def step():
         D.apply_circuit(gates, state, n=n, scratch=scratch, marshalled=arr, ctx=ctx)

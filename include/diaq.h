@@ -428,6 +428,25 @@ typedef struct diaq_tuning {
   uint64_t spmv_group_qubits; /* when non-zero, bit q says whether tiles are
                               paired across coupling qubit q (a per-qubit
                               choice that replaces spmv_group_min_qubit) */
+  /* Alg. 3 (plan.kron) kernels */
+  int32_t kron_stage_qubit; /* an operation of at most four qubits whose lowest
+                              qubit is below this is staged through LDS
+                              (0: default 3; -1: never) */
+  int32_t kron_split;      /* dense groups of four and five qubits: 0 default,
+                              1 one lane per coset (2^k amplitudes in
+                              registers), 2 the rows of 64 cosets split over
+                              the waves of a block, 8 rows per wave (inputs
+                              streamed from LDS), 3 the same with 4 rows per
+                              wave, 4 fp64 matrix-core products of 16 cosets
+                              at a time (groups whose qubits are all >= 4;
+                              others take the default), the matrix re-read
+                              from LDS for every tile, 5 the same with the
+                              matrix held in registers, 6 rows split as in 2
+                              with five-qubit products formed from three
+                              real multiplications per complex one */
+  int32_t kron_nontemporal;/* per-coset Alg. 3 kernel state streams: 0 default,
+                              1 non-temporal hints, -1 plain accesses */
+  int32_t kron_reserved;
 } diaq_tuning_t;
 
 diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);

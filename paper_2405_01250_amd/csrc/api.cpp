@@ -265,6 +265,11 @@ static diaq_status_t check_tuning(const diaq_tuning_t* t) {
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_group_min_qubit must be in [0, 63]");
   if (t->spmv_xcd_runs != 0 && t->spmv_xcd_runs != -1)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_xcd_runs must be 0 or -1");
+  if (t->kron_stage_qubit < -1 || t->kron_stage_qubit > 6)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_stage_qubit must be in [-1, 6]");
+  if (t->kron_split < 0 || t->kron_split > 6) return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_split must be in [0, 6]");
+  if (t->kron_nontemporal < -1 || t->kron_nontemporal > 1)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_nontemporal must be -1, 0 or 1");
   return DIAQ_OK;
 }
 

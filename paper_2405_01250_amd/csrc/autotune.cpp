@@ -137,6 +137,16 @@ std::vector<diaq_tuning_t> candidates() {
   return c;
 }
 
+// The SpMV autotuner chooses the product-kernel knobs only; the others
+// (expansion, workspace padding, Alg. 3 kernels) keep their current values.
+void keep_other_knobs(const diaq_tuning_t& cur, diaq_tuning_t* best) {
+  best->expand_nontemporal = cur.expand_nontemporal;
+  best->diag_pad = cur.diag_pad;
+  best->kron_stage_qubit = cur.kron_stage_qubit;
+  best->kron_split = cur.kron_split;
+  best->kron_nontemporal = cur.kron_nontemporal;
+}
+
 }  // namespace
 
 }  // namespace diaq
@@ -154,8 +164,7 @@ diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype,
     const std::string key = cache_key(ctx->device, nqubits, dtype);
     diaq_tuning_t best{};
     if (cache_path && cache_lookup(cache_path, key, &best)) {
-      best.expand_nontemporal = ctx->tuning.expand_nontemporal;
-      best.diag_pad = ctx->tuning.diag_pad;
+      keep_other_knobs(ctx->tuning, &best);
       ctx->tuning = best;
       if (out) *out = best;
       return DIAQ_OK;
@@ -293,8 +302,7 @@ diaq_status_t diaq_autotune(diaq_ctx_t ctx, int32_t nqubits, diaq_dtype_t dtype,
       // a mask of zero means "no per-qubit choice": keep one unused high bit
       best.spmv_group_qubits = mask ? mask : (uint64_t(1) << 63);
     }
-    best.expand_nontemporal = saved.expand_nontemporal;
-    best.diag_pad = saved.diag_pad;
+    keep_other_knobs(saved, &best);
     ctx->tuning = best;
     if (cache_path) DIAQ_TRY(cache_store(cache_path, key, best, total[bi]));
     if (out) *out = best;

@@ -173,7 +173,7 @@ diaq_status_t run_kron(diaq_ctx* ctx, const std::vector<FusedOp>& ops, int n, di
   std::vector<double> mats, m;
   OpTables tabs;
   for (size_t k = 0; k < ops.size(); k++) {
-    if (staged_dense(ops[k].core, n, int(ops[k].post.size()), &m, stg[k].S, &stg[k].k)) {
+    if (staged_dense(ops[k].core, n, int(ops[k].post.size()), ctx->tuning, dt, &m, stg[k].S, &stg[k].k)) {
       stg[k].moff = mats.size();
       mats.insert(mats.end(), m.begin(), m.end());
       tabs.add(ops[k].post);

@@ -313,7 +313,8 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
 // group: true with the dense matrix (interleaved, over the sorted qubits S,
 // k of them) if lg qualifies at n qubits (`tables`: it carries factor
 // tables).  launch_staged then applies it in place.
-bool staged_dense(const LocalGate& lg, int n, int tables, std::vector<double>* mat, int* S, int* k);
+bool staged_dense(const LocalGate& lg, int n, int tables, const diaq_tuning_t& t, diaq_dtype_t dt,
+                  std::vector<double>* mat, int* S, int* k);
 diaq_status_t launch_staged(diaq_ctx* ctx, const int* S, int k, const double* dmat, const char* tabs, int nt, int n,
                             diaq_dtype_t dt, void* state);
 

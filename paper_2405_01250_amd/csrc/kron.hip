@@ -42,7 +42,7 @@ struct KronArgs {
   int32_t adjoint;
   int32_t nt;          // folded diagonal factors: tables at tabs
   int32_t rows;        // 1: the table headers hold this op's roff[r]
-  int32_t pad;
+  int32_t ntio;        // 1: state loads and stores carry non-temporal hints
   const char* tabs;
   const double* dmat;  // device 4 x 4 local matrix (k <= 2), replaces m
   double m[8][8][2];
@@ -57,6 +57,30 @@ __device__ __forceinline__ double mel(const KronArgs& a, int r, int c, int j) {
     return a.dmat[(r * 4 + c) * 2 + j];
   else
     return a.m[r][c][j];
+}
+
+// State accesses, non-temporal when nt (each amplitude is read and written
+// once per operation).
+template <typename V>
+__device__ __forceinline__ V kld(const V* p, bool nt) {
+  if (nt) {
+    typedef decltype(V{}.x) E;
+    typedef E N2 __attribute__((ext_vector_type(2)));
+    const N2 t = __builtin_nontemporal_load(reinterpret_cast<const N2*>(p));
+    return V{t[0], t[1]};
+  }
+  return *p;
+}
+template <typename V>
+__device__ __forceinline__ void kst(V* p, const V& v, bool nt) {
+  if (nt) {
+    typedef decltype(V{}.x) E;
+    typedef E N2 __attribute__((ext_vector_type(2)));
+    N2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<N2*>(p));
+  } else {
+    *p = v;
+  }
 }
 
 __device__ __forceinline__ int64_t insert_zeros(int64_t v, const KronArgs& a) {
@@ -106,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
     ok[u] = ok[u] && ((uint64_t(base[u]) & a.cmask) == a.cmask);
 #pragma unroll
     for (int r = 0; r < d; r++) {
-      V t = ok[u] ? v[base[u] + a.off[r]] : V{0, 0};
+      V t = ok[u] ? kld(v + base[u] + a.off[r], a.ntio != 0) : V{0, 0};
       xr[u][r] = double(t.x);
       xi[u][r] = double(t.y);
     }
@@ -124,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
 #pragma unroll
     for (int r = 0; r < d; r++) {
       if (a.nt && !rows) apply_tables(a.tabs, a.nt, uint64_t(base[u] + a.off[r]), yr[r], yi[r]);
-      v[base[u] + a.off[r]] = V{R(yr[r]), R(yi[r])};
+      kst(v + base[u] + a.off[r], V{R(yr[r]), R(yi[r])}, a.ntio != 0);
     }
   }
   // rows whose controls are 0 keep their amplitude, but folded factors
@@ -155,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
     const bool on = (uint64_t(i) & a.cmask) == a.cmask;
     if (!on && a.nt == 0) continue;  // an unfolded controlled phase leaves these rows alone
-    V t = v[i];
+    V t = kld(v + i, a.ntio != 0);
     double tr = double(t.x), ti = double(t.y);
     if (on) {
       int r = 0;
@@ -167,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
       tr = nr;
     }
     if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(i), tr, ti);
-    v[i] = V{R(tr), R(ti)};
+    kst(v + i, V{R(tr), R(ti)}, a.ntio != 0);
   }
 }
 
@@ -342,6 +366,16 @@ diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGa
   KronArgs a = make_args(lg, n, adjoint, tabs, nt);
   a.dmat = dmat;
   a.rows = rows ? 1 : 0;
+  // non-temporal state streams (complex128; measured at n = 28: U3 5.65 ->
+  // 6.06 TB/s mean over the target qubits, diagonal gates 5.98 -> 6.31) when
+  // every row of a cache line is rewritten: a control below the line size
+  // without factor tables leaves every other row untouched, and such
+  // partial lines stream slower with the hints (CZ with control 0: 2.76 ->
+  // 2.14 TB/s); complex64 streams measured faster without
+  const uint64_t line_rows = dt == DIAQ_C128 ? 7 : 15;
+  const bool full_lines = (lg.cmask & line_rows) == 0 || nt > 0;
+  const int knob = ctx->tuning.kron_nontemporal;
+  a.ntio = (knob > 0 || (knob == 0 && dt == DIAQ_C128)) && full_lines ? 1 : 0;
   const int64_t N = int64_t(1) << n;
   const bool diag = is_diagonal_local(lg);
   if (dt == DIAQ_C128) {

@@ -233,14 +233,23 @@ __global__ __launch_bounds__(kBigBlock) void kron_big_kernel(BigArgs a, typename
 // that is bit 0 and the lanes already sit in consecutive slots).
 constexpr int kLdsLanes = 64;
 constexpr int kLdsCosetBits = 6;
-// A group of up to four qubits is staged when it has a qubit below 3; a
-// five-qubit group only when it holds qubit 0 (its 32 x 32 product is close
-// to the memory time, and the staged kernel, with fewer waves per CU,
-// overlaps the two less well: measured 1.9 ms per n = 28 operation on the
-// per-coset path against 3.3 ms staged for qubits 1-5, 2.9 against 2.8 for
-// qubits 0-4).
-constexpr int kLowQubit = 3;
-inline bool staged(const int* q, int k) { return k >= 1 && (k <= 4 ? q[0] < kLowQubit : q[0] == 0); }
+// A group of up to four qubits is staged when it has a qubit below 6 (the
+// per-coset lanes of a gate on qubit 3..5 read every other 2^q-element run,
+// two cache lines per 16-byte element load: U3 at n = 28 on qubits 3-5,
+// 5.5 -> 6.1 TB/s staged; complex64 keeps qubits below 3, as its staged
+// four-qubit groups measured slower: 3.9 against 4.9 TB/s on the per-coset
+// path one qubit higher); a five-qubit group only when it holds qubit 0
+// (its 32 x 32 product is close to the memory time, and the staged kernel,
+// with fewer waves per CU, overlaps the two less well: measured 1.9 ms per
+// n = 28 operation on the per-coset path against 3.3 ms staged for qubits
+// 1-5, 2.9 against 2.8 for qubits 0-4).
+constexpr int kLowQubit = 6, kLowQubit64 = 3;
+inline bool staged(const int* q, int k, int low) { return k >= 1 && (k <= 4 ? q[0] < low : q[0] == 0); }
+// the staging threshold of the knobs (kron_stage_qubit: 0 default, -1 never)
+inline int stage_low(const diaq_tuning_t& t, diaq_dtype_t dt) {
+  if (t.kron_stage_qubit == 0) return dt == DIAQ_C128 ? kLowQubit : kLowQubit64;
+  return t.kron_stage_qubit < 0 ? 0 : t.kron_stage_qubit;
+}
 
 struct LdsArgs {
   int32_t npos;
@@ -352,6 +361,238 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
   }
 }
 
+// Dense groups with the rows split over the waves of a block.  The block
+// stages 64 cosets in LDS exactly as kron_lds_kernel does; wave p then forms
+// rows [p L, (p + 1) L) of every coset, taking the coset's 2^K inputs out of
+// LDS one at a time, so a lane holds only its L output rows (not the 2^K
+// inputs) and the kernel needs few enough registers for five blocks of a
+// five-qubit group per CU: while some blocks multiply, others stream.
+// (The per-coset kernel keeps all 32 amplitudes of a five-qubit coset in
+// registers, 211 VGPRs, two waves per SIMD, and its 4096 FMAs per coset
+// barely overlap with its memory phase.)
+// G3: the matrix is given as (Re, Im, Re + Im) per entry and each complex
+// product takes three real FMAs instead of four (3072 instead of 4096 per
+// five-qubit coset).
+template <typename R, int K, int PARTS, bool G3>
+__global__ __launch_bounds__(kLdsLanes * PARTS) void kron_split_kernel(LdsArgs a, typename Vec<R>::V* __restrict__ v) {
+  using V = typename Vec<R>::V;
+  constexpr int D = 1 << K;
+  constexpr int E = kLdsLanes * D;
+  constexpr int T = kLdsLanes * PARTS;  // lanes per block
+  constexpr int L = D / PARTS;           // rows per lane, loads per lane
+  __shared__ double2 sx[E];
+  const int tid = threadIdx.x;
+  typedef __attribute__((address_space(4))) const double GD;
+  GD* mp = (GD*)(a.mat);
+  const int part = __builtin_amdgcn_readfirstlane(tid / kLdsLanes);
+  int64_t base = blockIdx.x;
+  for (int j = 0; j < a.npos; j++) {
+    const int p = a.pos[j];
+    base = (base & ((int64_t(1) << p) - 1)) | ((base >> p) << (p + 1));
+  }
+  const int64_t tid_el = base + staging_to_element(a, tid);
+  {
+    V t[L];
+#pragma unroll
+    for (int j = 0; j < L; j++) t[j] = bld(v + tid_el + a.joff[j * PARTS], a.nt_io != 0);
+#pragma unroll
+    for (int j = 0; j < L; j++) sx[slot(a, tid + j * T)] = double2{double(t[j].x), double(t[j].y)};
+  }
+  __syncthreads();
+  const int lane = tid & (kLdsLanes - 1);
+  int el = 0;
+  int64_t lo = 0;
+#pragma unroll
+  for (int i = 0; i < kLdsCosetBits; i++)
+    if ((lane >> i) & 1) {
+      el |= 1 << a.lane_e[i];
+      lo |= a.lane_off[i];
+    }
+  const int r0 = part * L;
+  double ar[L], ai[L];
+  if constexpr (G3) {
+    // three real products per complex one (Gauss): with m = a + i b and
+    // x = c + i d, Re = sum a c - sum b d and Im = sum (a + b)(c + d) -
+    // sum a c - sum b d; the table holds (a, b, a + b) per entry
+    double p1[L], p2[L], p3[L];
+#pragma unroll
+    for (int rr = 0; rr < L; rr++) p1[rr] = p2[rr] = p3[rr] = 0;
+#pragma unroll 4
+    for (int q = 0; q < D; q++) {
+      const double2 t = sx[slot(a, el + a.eoff[q])];
+      const double sum = t.x + t.y;
+#pragma unroll
+      for (int rr = 0; rr < L; rr++) {
+        const int m = 3 * ((r0 + rr) * D + q);
+        p1[rr] = fma(mp[m], t.x, p1[rr]);
+        p2[rr] = fma(mp[m + 1], t.y, p2[rr]);
+        p3[rr] = fma(mp[m + 2], sum, p3[rr]);
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < L; rr++) {
+      ar[rr] = p1[rr] - p2[rr];
+      ai[rr] = p3[rr] - p1[rr] - p2[rr];
+    }
+  } else {
+#pragma unroll
+    for (int rr = 0; rr < L; rr++) ar[rr] = ai[rr] = 0;
+    // column by column: one input out of LDS, then its L products
+#pragma unroll 4
+    for (int q = 0; q < D; q++) {
+      const double2 t = sx[slot(a, el + a.eoff[q])];
+#pragma unroll
+      for (int rr = 0; rr < L; rr++) {
+        const int m = 2 * ((r0 + rr) * D + q);
+        const double mr = mp[m], mi = mp[m + 1];
+        ar[rr] = fma(mr, t.x, fma(-mi, t.y, ar[rr]));
+        ai[rr] = fma(mr, t.y, fma(mi, t.x, ai[rr]));
+      }
+    }
+  }
+  // every wave has read its inputs before any output overwrites them
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < L; rr++) {
+    double yr = ar[rr], yi = ai[rr];
+    if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(base + lo + a.roff[r0 + rr]), yr, yi);
+    sx[slot(a, el + a.eoff[r0 + rr])] = double2{yr, yi};
+  }
+  __syncthreads();
+  {
+    double2 t[L];
+#pragma unroll
+    for (int j = 0; j < L; j++) t[j] = sx[slot(a, tid + j * T)];
+#pragma unroll
+    for (int j = 0; j < L; j++) bst(v + tid_el + a.joff[j * PARTS], V{R(t[j].x), R(t[j].y)}, a.nt_io != 0);
+  }
+}
+
+// Dense groups on the fp64 matrix cores.  A group's 2^K x 2^K complex
+// matrix M acts on [Re x; Im x] as the real 2D x 2D matrix
+// [[Re M, -Im M], [Im M, Re M]] (D = 2^K), so applying it to 16 cosets at
+// once is a real (2D x 2D) * (2D x 16) product: 2D / 16 row tiles of
+// v_mfma_f64_16x16x4f64, each accumulated over 2D / 4 slices of depth 4.
+// Lane l of a wave holds column l % 16 (one coset) at depth l / 16 of every
+// operand, so it loads its coset's inputs 4 s + l / 16 (s < D / 4) straight
+// from the state: real parts feed the first D / 4 slices, imaginary parts
+// the last D / 4.  Accumulator register j of lane l holds row 4 j + l / 16
+// of tile i (measured layout), so the lane ends up with the complete outputs
+// 16 i + 4 j + l / 16 (j < 4) of its coset, which it writes back in place; a wave owns its
+// 16 cosets, so every input is read before any output of the tile is
+// written.  The real matrix sits in LDS in operand order (one 8-byte read
+// per lane per product, conflict-free) and is loaded once per block;
+// blocks stay resident and step through the tiles.  The arithmetic (4096
+// FMAs per five-qubit coset) runs on the matrix cores, which leaves the
+// vector unit to address and move the state (the per-coset vector kernel
+// issues every FMA itself and spends 211 VGPRs on it).
+typedef double MfmaAcc __attribute__((ext_vector_type(4)));
+constexpr int kMfmaBlock = 256;
+
+struct MfmaArgs {
+  int64_t ntiles;      // cosets / 16
+  int32_t nt;          // factor tables at tabs
+  int32_t nt_io;       // non-temporal state streams
+  int32_t sorted[5];   // group qubits ascending
+  int32_t pad;
+  int64_t off[32];     // element offset of local index r
+  const double* lmat;  // real matrix in operand order, [(i S + s) 64 + lane]
+  const char* tabs;
+};
+
+// HOLD: the matrix operands stay in registers across tiles (the compiler
+// hoists the loop-invariant LDS reads: 128 VGPRs for a five-qubit group,
+// two waves per SIMD); otherwise every tile re-reads them from LDS (an
+// opaque per-tile offset keeps the reads in the loop, about 80 VGPRs).
+template <typename R, int K, bool HOLD>
+__global__ __launch_bounds__(kMfmaBlock) void kron_mfma_kernel(MfmaArgs a, typename Vec<R>::V* __restrict__ v) {
+  using V = typename Vec<R>::V;
+  constexpr int D = 1 << K;
+  constexpr int RT = 2 * D / 16;  // row tiles
+  constexpr int S = 2 * D / 4;    // slices of depth 4
+  constexpr int NX = D / 4;       // complex inputs per lane
+  __shared__ double sm[RT * S * 64];
+  for (int e = threadIdx.x; e < RT * S * 64; e += kMfmaBlock) sm[e] = a.lmat[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t waves = int64_t(gridDim.x) * (kMfmaBlock / 64);
+  for (int64_t t = int64_t(blockIdx.x) * (kMfmaBlock / 64) + (threadIdx.x >> 6); t < a.ntiles; t += waves) {
+    int64_t base = t * 16 + col;
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      const int p = a.sorted[j];
+      base = (base & ((int64_t(1) << p) - 1)) | ((base >> p) << (p + 1));
+    }
+    double xr[NX], xi[NX];
+#pragma unroll
+    for (int s = 0; s < NX; s++) {
+      const V x = bld(v + base + a.off[4 * s + kq], a.nt_io != 0);
+      xr[s] = double(x.x);
+      xi[s] = double(x.y);
+    }
+    MfmaAcc acc[RT];
+#pragma unroll
+    for (int i = 0; i < RT; i++) acc[i] = MfmaAcc{0, 0, 0, 0};
+    int mo = lane;
+    if constexpr (!HOLD) asm volatile("" : "+v"(mo));  // not loop-invariant: no hoisting
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+      const double b = s < NX ? xr[s] : xi[s - NX];
+#pragma unroll
+      for (int i = 0; i < RT; i++)
+        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(sm[(i * S + s) * 64 + mo], b, acc[i], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < RT / 2; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int r = 16 * i + 4 * j + kq;
+        double yr = acc[i][j], yi = acc[i + RT / 2][j];
+        const int64_t e = base + a.off[r];
+        if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(e), yr, yi);
+        bst(v + e, V{R(yr), R(yi)}, a.nt_io != 0);
+      }
+  }
+}
+
+// The real form of the D x D complex matrix m (row-major, interleaved) in
+// the operand order of kron_mfma_kernel: entry (i S + s) 64 + l holds
+// row 16 i + l % 16, column 4 s + l / 16 of [[Re, -Im], [Im, Re]].
+std::vector<double> mfma_operands(const std::vector<Cd>& m, int k) {
+  const int D = 1 << k, RT = 2 * D / 16, S = 2 * D / 4;
+  std::vector<double> out(size_t(RT) * S * 64);
+  for (int i = 0; i < RT; i++)
+    for (int s = 0; s < S; s++)
+      for (int l = 0; l < 64; l++) {
+        const int row = 16 * i + l % 16, c = 4 * s + l / 16;
+        const Cd z = m[size_t(row % D) * D + (c % D)];
+        double val;
+        if (row < D) val = c < D ? z.real() : -z.imag();
+        else val = c < D ? z.imag() : z.real();
+        out[(size_t(i) * S + s) * 64 + l] = val;
+      }
+  return out;
+}
+
+// The matrix-core kernel needs 16 cosets of consecutive elements per tile
+// (every group qubit >= 4) and at least one tile.
+inline bool mfma_group(const int* q, int k, int n) { return (k == 4 || k == 5) && q[0] >= 4 && n >= k + 4; }
+
+template <typename R>
+void launch_mfma(const MfmaArgs& a, int k, bool hold, int num_cus, hipStream_t stream, void* state) {
+  using V = typename Vec<R>::V;
+  const int64_t want = (a.ntiles + 3) / 4;
+  // resident blocks: four (16 waves) per CU, two when a five-qubit
+  // group's matrix is held in registers
+  const int64_t resident = int64_t(num_cus) * ((hold && k == 5) ? 2 : 4);
+  const dim3 grid(unsigned(std::max<int64_t>(1, std::min(want, resident)))), block(kMfmaBlock);
+  V* v = static_cast<V*>(state);
+  if (k == 4) hipLaunchKernelGGL((kron_mfma_kernel<R, 4, true>), grid, block, 0, stream, a, v);
+  else if (hold) hipLaunchKernelGGL((kron_mfma_kernel<R, 5, true>), grid, block, 0, stream, a, v);
+  else hipLaunchKernelGGL((kron_mfma_kernel<R, 5, false>), grid, block, 0, stream, a, v);
+}
+
 // Staging layout for the group S (ascending) on n qubits; false if the
 // state has fewer than 64 cosets.
 bool make_lds_args(const int* S, int k, int n, LdsArgs* a) {
@@ -405,6 +646,25 @@ bool make_lds_args(const int* S, int k, int n, LdsArgs* a) {
   return true;
 }
 
+// rows = 8 or 4 output rows per wave (k = 4 or 5); g3: a.mat holds the
+// (Re, Im, Re + Im) table of the three-multiplication product
+template <typename R>
+void launch_split(const LdsArgs& a, int k, int rows, bool g3, int n, hipStream_t stream, void* state) {
+  using V = typename Vec<R>::V;
+  const dim3 grid(unsigned((int64_t(1) << n) >> (k + kLdsCosetBits)));
+  V* v = static_cast<V*>(state);
+  if (k == 4 && rows == 8)
+    hipLaunchKernelGGL((kron_split_kernel<R, 4, 2, false>), grid, dim3(kLdsLanes * 2), 0, stream, a, v);
+  else if (k == 4)
+    hipLaunchKernelGGL((kron_split_kernel<R, 4, 4, false>), grid, dim3(kLdsLanes * 4), 0, stream, a, v);
+  else if (rows == 8 && g3)
+    hipLaunchKernelGGL((kron_split_kernel<R, 5, 4, true>), grid, dim3(kLdsLanes * 4), 0, stream, a, v);
+  else if (rows == 8)
+    hipLaunchKernelGGL((kron_split_kernel<R, 5, 4, false>), grid, dim3(kLdsLanes * 4), 0, stream, a, v);
+  else
+    hipLaunchKernelGGL((kron_split_kernel<R, 5, 8, false>), grid, dim3(kLdsLanes * 8), 0, stream, a, v);
+}
+
 template <typename R>
 void launch_lds(const LdsArgs& a, int k, int n, hipStream_t stream, void* state) {
   using V = typename Vec<R>::V;
@@ -422,7 +682,8 @@ void launch_lds(const LdsArgs& a, int k, int n, hipStream_t stream, void* state)
 
 }  // namespace
 
-bool staged_dense(const LocalGate& lg, int n, int tables, std::vector<double>* mat, int* S, int* k) {
+bool staged_dense(const LocalGate& lg, int n, int tables, const diaq_tuning_t& t, diaq_dtype_t dt,
+                  std::vector<double>* mat, int* S, int* k) {
   // uncontrolled operations, or ones whose factors touch every row anyway
   // (a controlled one without them reads only its control-on half)
   if (lg.nc && !tables) return false;
@@ -430,7 +691,7 @@ bool staged_dense(const LocalGate& lg, int n, int tables, std::vector<double>* m
   const int u = gate_qubit_list(lg, q);
   if (u > 4) return false;
   std::sort(q, q + u);
-  if (!staged(q, u)) return false;
+  if (!staged(q, u, stage_low(t, dt))) return false;
   LdsArgs probe;
   if (!make_lds_args(q, u, n, &probe)) return false;
   const std::vector<Cd> E = embed_gate(lg, q, u);
@@ -536,13 +797,32 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
   const int64_t N = int64_t(1) << n;
   // one table: every operation's matrix (2 D^2 doubles), then the factors
   std::vector<double> mats;
-  std::vector<size_t> moff(ops.size());
+  std::vector<size_t> moff(ops.size()), loff(ops.size(), SIZE_MAX);
   OpTables tabs;
+  const bool use_mfma = ctx->tuning.kron_split == 4 || ctx->tuning.kron_split == 5;
+  const bool g3 = ctx->tuning.kron_split == 6;
+  std::vector<size_t> loff3(ops.size(), SIZE_MAX);
   for (size_t k = 0; k < ops.size(); k++) {
     moff[k] = mats.size();
     for (const Cd& z : ops[k].m) {
       mats.push_back(z.real());
       mats.push_back(z.imag());
+    }
+    if (g3 && !ops[k].raw && ops[k].k == 5) {
+      // (Re, Im, Re + Im) per entry for the three-multiplication product
+      loff3[k] = mats.size();
+      for (const Cd& z : ops[k].m) {
+        mats.push_back(z.real());
+        mats.push_back(z.imag());
+        mats.push_back(z.real() + z.imag());
+      }
+    }
+    if (use_mfma && !ops[k].raw && mfma_group(ops[k].q, ops[k].k, n)) {
+      // the real form in operand order, 16-byte aligned
+      if (mats.size() & 1) mats.push_back(0.0);
+      loff[k] = mats.size();
+      const std::vector<double> lm = mfma_operands(ops[k].m, ops[k].k);
+      mats.insert(mats.end(), lm.begin(), lm.end());
     }
     tabs.add(ops[k].post);
   }
@@ -564,9 +844,47 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
     // (layered n = 28, groups of 4: 163 -> 155 ms); five-qubit groups
     // measured faster without
     const int ntp = (op.k <= 4 && dt == DIAQ_C128) ? 1 : 0;
+    // dense 4-5 qubit groups: complex128 splits the rows over the waves of a
+    // block by default (n = 28, mean over positions: four qubits with 4 rows
+    // per wave 5.46 -> 6.00 TB/s, five qubits with 8 rows 4.54 -> 4.70);
+    // complex64 keeps one lane per coset (its fp64 arithmetic, not memory,
+    // is the limit: split 4.21 against 4.76 TB/s for four qubits)
+    int split = ctx->tuning.kron_split;
+    if (split == 0) split = dt == DIAQ_C128 ? (op.k == 4 ? 3 : 2) : 1;
     if (op.raw) {
       DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, op.lg, n, dt, state, false, tk, nt));
-    } else if (staged(op.q, op.k) && make_lds_args(op.q, op.k, n, &la)) {
+    } else if (loff[k] != SIZE_MAX) {
+      // dense 4-5 qubit groups on the matrix cores
+      MfmaArgs ma;
+      std::memset(&ma, 0, sizeof(ma));
+      ma.ntiles = (N >> op.k) / 16;
+      ma.nt = nt;
+      ma.nt_io = ntp;
+      for (int j = 0; j < op.k; j++) ma.sorted[j] = op.q[j];
+      for (int r = 0; r < (1 << op.k); r++) {
+        int64_t o = 0;
+        for (int j = 0; j < op.k; j++)
+          if ((r >> j) & 1) o |= int64_t(1) << op.q[j];
+        ma.off[r] = o;
+      }
+      ma.lmat = dm + loff[k];
+      ma.tabs = tk;
+      const bool hold = ctx->tuning.kron_split == 5;
+      if (dt == DIAQ_C128) launch_mfma<double>(ma, op.k, hold, ctx->num_cus, ctx->stream, state);
+      else launch_mfma<float>(ma, op.k, hold, ctx->num_cus, ctx->stream, state);
+      DIAQ_HIP(hipGetLastError());
+    } else if (op.k >= 4 && split >= 2 && split != 4 && split != 5 && make_lds_args(op.q, op.k, n, &la)) {
+      // dense 4-5 qubit groups, rows split over the waves of a block
+      const bool three = loff3[k] != SIZE_MAX;
+      la.mat = dm + (three ? loff3[k] : moff[k]);
+      la.tabs = tk;
+      la.nt = nt;
+      la.nt_io = ntp;
+      const int rows = split == 3 ? 4 : 8;
+      if (dt == DIAQ_C128) launch_split<double>(la, op.k, rows, three, n, ctx->stream, state);
+      else launch_split<float>(la, op.k, rows, three, n, ctx->stream, state);
+      DIAQ_HIP(hipGetLastError());
+    } else if (staged(op.q, op.k, stage_low(ctx->tuning, dt)) && make_lds_args(op.q, op.k, n, &la)) {
       la.mat = dm + moff[k];
       la.tabs = tk;
       la.nt = nt;

@@ -56,7 +56,9 @@ class diaq_tuning_t(ctypes.Structure):
     _fields_ = [("spmv_rows", ctypes.c_int32), ("spmv_group_bits", ctypes.c_int32), ("spmv_chunk", ctypes.c_int32),
                 ("spmv_nontemporal", ctypes.c_int32), ("spmv_group_min_qubit", ctypes.c_int32),
                 ("expand_nontemporal", ctypes.c_int32), ("diag_pad", ctypes.c_int32),
-                ("spmv_xcd_runs", ctypes.c_int32), ("spmv_group_qubits", ctypes.c_uint64)]
+                ("spmv_xcd_runs", ctypes.c_int32), ("spmv_group_qubits", ctypes.c_uint64),
+                ("kron_stage_qubit", ctypes.c_int32), ("kron_split", ctypes.c_int32),
+                ("kron_nontemporal", ctypes.c_int32), ("kron_reserved", ctypes.c_int32)]
 
 
 class diaq_spmv_shape_t(ctypes.Structure):
@@ -578,7 +580,7 @@ def get_tuning(ctx: Context | None = None) -> dict:
     ctx = ctx or context()
     t = diaq_tuning_t()
     _check(load().diaq_get_tuning(ctx.handle, ctypes.byref(t)))
-    return {f: getattr(t, f) for f, _ in diaq_tuning_t._fields_ if f != "reserved"}
+    return {f: getattr(t, f) for f, _ in diaq_tuning_t._fields_ if not f.endswith("reserved")}
 
 
 def profile_start(ctx: Context | None = None):
@@ -728,7 +730,7 @@ def autotune(n: int, dtype=torch.complex128, cache_path: str | None = None, ctx:
     t = diaq_tuning_t()
     _check(load().diaq_autotune(ctx.handle, n, _dtype_code(dtype),
                                 cache_path.encode() if cache_path else None, ctypes.byref(t)))
-    return {f: getattr(t, f) for f, _ in diaq_tuning_t._fields_ if f != "reserved"}
+    return {f: getattr(t, f) for f, _ in diaq_tuning_t._fields_ if not f.endswith("reserved")}
 
 
 def autotune_plan(gates: Sequence, n: int, dtype=torch.complex128, allow_kron: bool = False, measure: int = 3,
