@@ -45,13 +45,17 @@ def _args():
     ap.add_argument("--extras", type=int, default=1, help="also time adjoint vs parameter shift (HEA n=20)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of autotuned product-kernel knobs (read if it holds this size, else written)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "sweep"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "sweep", "plan"],
                     help="copy: run a plain device copy of 2^n complex elements (counter calibration); "
                          "sweep: single-gate rates per target qubit (one JSON line per gate)")
     ap.add_argument("--sweep-plan", default="dia", choices=["dia", "kron", "groups"],
                     help="sweep: dia = expansion + DiaQ SpMV per gate; kron = Alg. 3 in-place product per "
                          "gate; groups = Alg. 3 fused dense groups of 3, 4 and 5 consecutive qubits")
     ap.add_argument("--sweep-dtypes", default="c128,c64", help="sweep: dtypes to run")
+    ap.add_argument("--sweep-gates", default="", help="sweep: comma-separated gate shapes to run (default all)")
+    ap.add_argument("--sweep-qubits", default="", help="sweep: first,last target qubit (default all)")
+    ap.add_argument("--plan", default="kron+fuse4",
+                    help="mode plan: the benchmark circuit under this plan only, e.g. kron, kron+fuse4, dia+fuse3")
     ap.add_argument("--knobs", default="", help="JSON object of tuning knobs set after autotuning "
                                                 "(fields of diaq_tuning_t), e.g. '{\"kron_split\": 2}'")
     return ap.parse_args()
@@ -240,6 +244,12 @@ def sweep_mode(a):
                     gates = _group_circuit(W, rng, list(range(q, q + k)))
                     assert D.plan_count(gates, n, plan, dtype=tdt)[0] == 1
                     cases.append(("G%d" % k, q, gates, plan))
+        if a.sweep_gates:
+            keep = set(a.sweep_gates.split(","))
+            cases = [c for c in cases if c[0] in keep]
+        if a.sweep_qubits:
+            lo, hi = (int(v) for v in a.sweep_qubits.split(","))
+            cases = [c for c in cases if lo <= c[1] <= hi]
         for name, q, g, plan in cases:
             arr = D.gate_array(g)
             D.apply_circuit(g, psi, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
@@ -257,6 +267,59 @@ def sweep_mode(a):
         torch.cuda.empty_cache()
 
 
+def _plan_of(name, D):
+    """'dia', 'kron', 'dia+fuseK' or 'kron+fuseK' -> a diaq_plan_t."""
+    base, _, fuse = name.partition("+fuse")
+    if base not in ("dia", "kron"):
+        raise SystemExit("unknown plan %r" % name)
+    kw = {"kron": base == "kron"}
+    if fuse:
+        kw.update(fuse=True, max_fused_qubits=int(fuse))
+    return D.make_plan(**kw)
+
+
+def plan_mode(a):
+    """The benchmark circuit under one plan (--plan) for --warmup untimed
+    and --steps timed runs: logical gates/s, and the operations' algorithmic
+    rate from HIP events around every launch (Alg. 3: 2 N s per operation,
+    N s for a controlled one without factors)."""
+    import torch
+
+    from paper_2405_01250_amd import diaq as D
+    from paper_2405_01250_amd import inputs as W
+
+    n = a.n
+    tdt = torch.complex128 if a.dtype == "c128" else torch.complex64
+    gates = W.random_layered(n, a.layers, a.seed)
+    arr = D.gate_array(gates)
+    plan = _plan_of(a.plan, D)
+    ctx = D.context()
+    D.autotune(n, dtype=tdt, cache_path=a.tune_cache, ctx=ctx)
+    if a.knobs:
+        D.set_tuning(ctx, **json.loads(a.knobs))
+    state = torch.zeros(1 << n, dtype=tdt, device="cuda:0")
+    state[0] = 1
+    scratch = torch.empty_like(state)
+    nops, nbytes = D.plan_count(gates, n, plan, dtype=tdt)
+    for _ in range(max(1, a.warmup)):
+        D.apply_circuit(gates, state, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    D.profile_start(ctx)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        D.apply_circuit(gates, state, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    p = D.profile_stop(ctx)
+    print(json.dumps({"mode": "plan", "plan": a.plan, "dtype": a.dtype, "n": n, "gates": len(gates), "ops": nops,
+                      "steps": a.steps, "ms_per_step": round(dt / a.steps * 1e3, 3),
+                      "gates_per_s": round(len(gates) * a.steps / dt, 2),
+                      "op_launches": p["spmv_launches"], "op_avg_us": round(p["spmv_ms"] / max(1, p["spmv_launches"]) * 1e3, 2),
+                      "op_GBps": round(p["spmv_bytes"] / p["spmv_ms"] / 1e6, 1) if p["spmv_ms"] else None,
+                      "op_bytes_per_launch": p["spmv_bytes"] / max(1, p["spmv_launches"]),
+                      "tuning": D.get_tuning(ctx)}), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -268,6 +331,9 @@ def main():
         return
     if a.mode == "sweep":
         sweep_mode(a)
+        return
+    if a.mode == "plan":
+        plan_mode(a)
         return
     import numpy as np
     import torch
