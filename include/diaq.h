@@ -446,7 +446,12 @@ typedef struct diaq_tuning {
                               real multiplications per complex one */
   int32_t kron_nontemporal;/* per-coset Alg. 3 kernel state streams: 0 default,
                               1 non-temporal hints, -1 plain accesses */
-  int32_t kron_reserved;
+  int32_t kron_small_qubits; /* plan.kron on at most this many qubits runs
+                              the whole circuit in LDS, one launch per run of
+                              gates whose matrices fit the kernel arguments
+                              (0: default, as many qubits as the state fits
+                              in LDS, held as complex128 either way: 13 on
+                              160 KiB; -1: never) */
 } diaq_tuning_t;
 
 diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);

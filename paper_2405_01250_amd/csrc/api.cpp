@@ -234,6 +234,9 @@ diaq_status_t diaq_create(int32_t device, void* hip_stream, diaq_ctx_t* out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    c->lds_bytes = lds;
   *out = c;
   clear_error();
   return DIAQ_OK;
@@ -270,6 +273,8 @@ static diaq_status_t check_tuning(const diaq_tuning_t* t) {
   if (t->kron_split < 0 || t->kron_split > 6) return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_split must be in [0, 6]");
   if (t->kron_nontemporal < -1 || t->kron_nontemporal > 1)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_nontemporal must be -1, 0 or 1");
+  if (t->kron_small_qubits < -1 || t->kron_small_qubits > 14)
+    return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_small_qubits must be in [-1, 14]");
   return DIAQ_OK;
 }
 

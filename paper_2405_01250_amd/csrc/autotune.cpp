@@ -158,6 +158,7 @@ void keep_other_knobs(const diaq_tuning_t& cur, diaq_tuning_t* best) {
   best->kron_stage_qubit = cur.kron_stage_qubit;
   best->kron_split = cur.kron_split;
   best->kron_nontemporal = cur.kron_nontemporal;
+  best->kron_small_qubits = cur.kron_small_qubits;
 }
 
 }  // namespace

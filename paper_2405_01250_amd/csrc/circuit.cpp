@@ -226,7 +226,14 @@ diaq_status_t apply_range(diaq_ctx* ctx, const diaq_gate_t* gates, int64_t begin
   void* res = nullptr;
   diaq_status_t st;
   const int kmax = plan && plan->max_fused_qubits ? plan->max_fused_qubits : 2;
-  if (plan && plan->kron && plan->fuse && kmax > 3) {
+  if (plan && plan->kron && nqubits <= small_circuit_qubits(ctx, dtype)) {
+    // a small state: the whole range in LDS, one launch per run of gates
+    // (fusion buys nothing when no gate touches memory)
+    Prepared p;
+    st = prepare_gates(gates + begin, end - begin, nqubits, &p);
+    if (st == DIAQ_OK) st = run_small(ctx, p.lg, nqubits, dtype, state);
+    res = state;
+  } else if (plan && plan->kron && plan->fuse && kmax > 3) {
     // groups of four or five qubits: dense local matrices
     std::vector<BigOp> ops;
     st = plan_big(gates + begin, end - begin, nqubits, kmax, &ops);

@@ -97,6 +97,7 @@ struct diaq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cus = 256;
+  int lds_bytes = 65536;    // LDS one workgroup may allocate
   diaq::Workspace diag;     // expanded diagonals for circuit runs
   diaq::Workspace red;      // reduction partials
   diaq::Workspace aux;      // small per-call device tables
@@ -405,6 +406,12 @@ int64_t kron_adjoint_blocks(const LocalGate& lg, int n);
 diaq_status_t launch_kron_adjoint(diaq_ctx* ctx, hipStream_t stream, const LocalGate& lg, const LocalGate* gen,
                                   int n, diaq_dtype_t dt, void* psi, void* lam, double2* partial, bool step_back,
                                   const double* dmat = nullptr);
+// small.hip: the gates lg applied in order to a state small enough for
+// one workgroup's LDS (one launch per run of gates that fits the kernel
+// arguments), in place.
+diaq_status_t run_small(diaq_ctx* ctx, const std::vector<LocalGate>& lg, int n, diaq_dtype_t dt, void* state);
+// Largest register the one-launch path takes for the knobs and the device.
+int small_circuit_qubits(const diaq_ctx* ctx, diaq_dtype_t dt);
 // spmv.hip: one workgroup sums partial[0..count) into dres (2 doubles).
 // Algorithmic bytes of one Alg. 3 operation: every amplitude it changes is
 // read and written once.  Without folded factors only the rows whose

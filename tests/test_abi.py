@@ -265,3 +265,29 @@ def test_spmv_shape_host_only(lib):
         D.spmv_shape(W.u3(0.1, 0.2, 0.3, 28), 28)
     with pytest.raises(D.DiaqError):
         D.spmv_shape(W.u3(0.1, 0.2, 0.3, 3), 28, spmv_rows=3)
+
+
+def test_small_circuit_kernel_reads_gates_from_the_argument_segment():
+    """The one-launch small-state kernel reads its packed gates in place in
+    the kernel-argument segment: no private (scratch) copy of its arguments,
+    whose address would not be a constant-space address.  Checked on the
+    compiler's resource report for gfx950 (host-only)."""
+    src = os.path.join(ROOT, "paper_2405_01250_amd", "csrc", "small.hip")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    out = subprocess.run([hipcc, "-O3", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I",
+                          os.path.dirname(src), "--offload-arch=gfx950", "--cuda-device-only", "-c", src, "-o",
+                          os.devnull, "-Rpass-analysis=kernel-resource-usage"], capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr[-2000:]
+    scratch, cur = {}, None
+    for line in out.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and cur:
+            scratch[cur] = int(m.group(1))
+    kernels = {k: v for k, v in scratch.items() if "small_circuit_kernel" in k}
+    assert len(kernels) == 2, scratch
+    assert all(v == 0 for v in kernels.values()), kernels

@@ -19,6 +19,18 @@ TOL64 = 1e-12
 TOL32 = 1e-5
 
 
+@pytest.fixture(autouse=True)
+def per_gate_launches():
+    """These tests exercise the per-operation Alg. 3 kernels, also on small
+    states, so the one-launch LDS path for small states is switched off
+    (tests/test_gpu_small.py covers it)."""
+    ctx = D.context()
+    saved = D.get_tuning(ctx)
+    D.set_tuning(ctx, kron_small_qubits=-1)
+    yield
+    D.set_tuning(ctx, **saved)
+
+
 @pytest.mark.parametrize("fuse", [False, True])
 @pytest.mark.parametrize("seed", range(6))
 def test_kron_random_circuits(fuse, seed):
