@@ -452,6 +452,15 @@ typedef struct diaq_tuning {
                               (0: default, as many qubits as the state fits
                               in LDS, held as complex128 either way: 13 on
                               160 KiB; -1: never) */
+  int32_t kron_order;      /* order in which the workgroups of the Alg. 3
+                              kernels take their blocks of cosets: 0 default
+                              (per-coset kernel: XCD eighths for operations
+                              that rewrite every row, else launch order;
+                              staged and row-split group kernels: halves
+                              interleaved), 1 each XCD a contiguous eighth,
+                              2 the two halves interleaved, 3 blocks
+                              scattered by an odd multiplier */
+  int32_t kron_reserved;
 } diaq_tuning_t;
 
 diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);

@@ -275,6 +275,7 @@ static diaq_status_t check_tuning(const diaq_tuning_t* t) {
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_nontemporal must be -1, 0 or 1");
   if (t->kron_small_qubits < -1 || t->kron_small_qubits > 14)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_small_qubits must be in [-1, 14]");
+  if (t->kron_order < 0 || t->kron_order > 3) return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_order must be 0..3");
   return DIAQ_OK;
 }
 

@@ -159,6 +159,7 @@ void keep_other_knobs(const diaq_tuning_t& cur, diaq_tuning_t* best) {
   best->kron_split = cur.kron_split;
   best->kron_nontemporal = cur.kron_nontemporal;
   best->kron_small_qubits = cur.kron_small_qubits;
+  best->kron_order = cur.kron_order;
 }
 
 }  // namespace

@@ -43,6 +43,7 @@ struct KronArgs {
   int32_t nt;          // folded diagonal factors: tables at tabs
   int32_t rows;        // 1: the table headers hold this op's roff[r]
   int32_t ntio;        // 1: state loads and stores carry non-temporal hints
+  int32_t order;       // workgroup order (kron_block)
   const char* tabs;
   const double* dmat;  // device 4 x 4 local matrix (k <= 2), replaces m
   double m[8][8][2];
@@ -83,6 +84,19 @@ __device__ __forceinline__ void kst(V* p, const V& v, bool nt) {
   }
 }
 
+// The block of cosets workgroup b takes: launch order, each XCD (the
+// device deals workgroups to its 8 XCDs in turn) a contiguous eighth of the
+// blocks, or the two halves interleaved.
+__device__ __forceinline__ int64_t kron_block(int order) {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  if (order == 1 && (nb & 7) == 0) return (b & 7) * (nb >> 3) + (b >> 3);
+  if (order == 2 && (nb & 1) == 0) return (b >> 1) + (b & 1) * (nb >> 1);
+  // 3: blocks scattered over the state (an odd multiplier permutes a
+  // power-of-two count)
+  if (order == 3 && (nb & (nb - 1)) == 0) return (b * 0x9E3779B1ll) & (nb - 1);
+  return b;
+}
+
 __device__ __forceinline__ int64_t insert_zeros(int64_t v, const KronArgs& a) {
   for (int j = 0; j < a.k; j++) {
     const int p = a.sorted[j];
@@ -118,7 +132,7 @@ template <typename R, int K, bool DM, int TAB>
 __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename Vec<R>::V* __restrict__ v) {
   using V = typename Vec<R>::V;
   constexpr int d = 1 << K;
-  const int64_t c0 = int64_t(blockIdx.x) * (kBlock * kCosetsPerLane) + threadIdx.x;
+  const int64_t c0 = kron_block(a.order) * (kBlock * kCosetsPerLane) + threadIdx.x;
   int64_t base[kCosetsPerLane];
   bool ok[kCosetsPerLane];
   double xr[kCosetsPerLane][d], xi[kCosetsPerLane][d];
@@ -376,6 +390,13 @@ diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGa
   const bool full_lines = (lg.cmask & line_rows) == 0 || nt > 0;
   const int knob = ctx->tuning.kron_nontemporal;
   a.ntio = (knob > 0 || (knob == 0 && dt == DIAQ_C128)) && full_lines ? 1 : 0;
+  // XCD-contiguous order (each XCD streams its own eighth of the state;
+  // n = 28, U3 mean over qubits 8-27 6.04 -> 6.28 TB/s, qubits 20-22 5.5 ->
+  // 5.8-6.3; the two halves interleaved 6.08, blocks scattered 5.09) for
+  // operations that rewrite every row; a control without factor tables
+  // leaves whole regions idle, which that order would put on half the XCDs
+  // (CX controlled by the top qubit 5.25 -> 5.02)
+  a.order = ctx->tuning.kron_order != 0 ? ctx->tuning.kron_order : ((lg.cmask == 0 || nt > 0) ? 1 : 0);
   const int64_t N = int64_t(1) << n;
   const bool diag = is_diagonal_local(lg);
   if (dt == DIAQ_C128) {

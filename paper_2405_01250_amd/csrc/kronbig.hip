@@ -245,6 +245,14 @@ constexpr int kLdsCosetBits = 6;
 // 1-5, 2.9 against 2.8 for qubits 0-4).
 constexpr int kLowQubit = 6, kLowQubit64 = 3;
 inline bool staged(const int* q, int k, int low) { return k >= 1 && (k <= 4 ? q[0] < low : q[0] == 0); }
+// block order of the staged and row-split group kernels (every row of a
+// dense group is rewritten, so no region idles): by default the two halves
+// of the blocks interleaved (n = 28, complex128, mean over positions: four
+// qubits 5.96 -> 6.16 TB/s, worst position 3.9 -> 5.5 (groups across
+// qubits 17-20); three qubits staged below qubit 6 5.5 -> 6.0; five qubits
+// unchanged, 4.6; XCD eighths 5.98, scattered blocks 5.28)
+inline int group_order(const diaq_tuning_t& t) { return t.kron_order == 0 ? 2 : t.kron_order; }
+
 // the staging threshold of the knobs (kron_stage_qubit: 0 default, -1 never)
 inline int stage_low(const diaq_tuning_t& t, diaq_dtype_t dt) {
   if (t.kron_stage_qubit == 0) return dt == DIAQ_C128 ? kLowQubit : kLowQubit64;
@@ -262,7 +270,7 @@ struct LdsArgs {
   int32_t nt_io;     // non-temporal state streams
   int64_t lane_off[kLdsCosetBits];  // element offset of lane bit i
   int32_t lane_e[kLdsCosetBits];    // staging bit of lane bit i
-  int32_t pad;
+  int32_t order;                    // block order (lds_block)
   int32_t eoff[32];     // staging offset of local index r
   int64_t roff[32];     // element offset of local index r
   int64_t joff[32];     // element offset of staging index 64 j
@@ -282,6 +290,18 @@ __device__ __forceinline__ int64_t staging_to_element(const LdsArgs& a, int e) {
 
 __device__ __forceinline__ int slot(const LdsArgs& a, int e) { return e ^ ((e >> a.swz) & a.smask); }
 
+// The block of 64 cosets workgroup b stages: launch order, or each XCD (the
+// device deals workgroups to its 8 XCDs in turn) a contiguous eighth.
+__device__ __forceinline__ int64_t lds_block(int order) {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  if (order == 1 && (nb & 7) == 0) return (b & 7) * (nb >> 3) + (b >> 3);
+  if (order == 2 && (nb & 1) == 0) return (b >> 1) + (b & 1) * (nb >> 1);
+  // 3: blocks scattered over the state (an odd multiplier permutes a
+  // power-of-two count)
+  if (order == 3 && (nb & (nb - 1)) == 0) return (b * 0x9E3779B1ll) & (nb - 1);
+  return b;
+}
+
 // PARTS waves per block: wave p computes rows [p D / PARTS, (p + 1) D /
 // PARTS) of every coset, so the block shares one staged matrix and a
 // five-qubit group keeps enough waves per CU to overlap its arithmetic with
@@ -300,7 +320,7 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
   typedef __attribute__((address_space(4))) const double GD;
   GD* mp = (GD*)(a.mat);
   const int part = __builtin_amdgcn_readfirstlane(tid / kLdsLanes);
-  int64_t base = blockIdx.x;
+  int64_t base = lds_block(a.order);
   for (int j = 0; j < a.npos; j++) {
     const int p = a.pos[j];
     base = (base & ((int64_t(1) << p) - 1)) | ((base >> p) << (p + 1));
@@ -385,7 +405,7 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_split_kernel(LdsArgs a
   typedef __attribute__((address_space(4))) const double GD;
   GD* mp = (GD*)(a.mat);
   const int part = __builtin_amdgcn_readfirstlane(tid / kLdsLanes);
-  int64_t base = blockIdx.x;
+  int64_t base = lds_block(a.order);
   for (int j = 0; j < a.npos; j++) {
     const int p = a.pos[j];
     base = (base & ((int64_t(1) << p) - 1)) | ((base >> p) << (p + 1));
@@ -712,6 +732,7 @@ diaq_status_t launch_staged(diaq_ctx* ctx, const int* S, int k, const double* dm
   la.mat = dmat;
   la.tabs = tabs;
   la.nt = tabs ? nt : 0;
+  la.order = group_order(ctx->tuning);
   la.nt_io = (k <= 4 && dt == DIAQ_C128) ? 1 : 0;
   if (dt == DIAQ_C128) launch_lds<double>(la, k, n, ctx->stream, state);
   else launch_lds<float>(la, k, n, ctx->stream, state);
@@ -880,6 +901,7 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
       la.tabs = tk;
       la.nt = nt;
       la.nt_io = ntp;
+      la.order = group_order(ctx->tuning);
       const int rows = split == 3 ? 4 : 8;
       if (dt == DIAQ_C128) launch_split<double>(la, op.k, rows, three, n, ctx->stream, state);
       else launch_split<float>(la, op.k, rows, three, n, ctx->stream, state);
@@ -889,6 +911,7 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
       la.tabs = tk;
       la.nt = nt;
       la.nt_io = ntp;
+      la.order = group_order(ctx->tuning);
       if (dt == DIAQ_C128) launch_lds<double>(la, op.k, n, ctx->stream, state);
       else launch_lds<float>(la, op.k, n, ctx->stream, state);
       DIAQ_HIP(hipGetLastError());

@@ -58,7 +58,8 @@ class diaq_tuning_t(ctypes.Structure):
                 ("expand_nontemporal", ctypes.c_int32), ("diag_pad", ctypes.c_int32),
                 ("spmv_xcd_runs", ctypes.c_int32), ("spmv_group_qubits", ctypes.c_uint64),
                 ("kron_stage_qubit", ctypes.c_int32), ("kron_split", ctypes.c_int32),
-                ("kron_nontemporal", ctypes.c_int32), ("kron_small_qubits", ctypes.c_int32)]
+                ("kron_nontemporal", ctypes.c_int32), ("kron_small_qubits", ctypes.c_int32),
+                ("kron_order", ctypes.c_int32), ("kron_reserved", ctypes.c_int32)]
 
 
 class diaq_spmv_shape_t(ctypes.Structure):

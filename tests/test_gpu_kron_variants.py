@@ -34,6 +34,9 @@ _KNOBS = {
     "mfma": {"kron_split": 4},
     "mfma_hold": {"kron_split": 5},
     "split8_gauss": {"kron_split": 6},
+    "order_xcd": {"kron_order": 1, "kron_stage_qubit": -1},
+    "order_halves": {"kron_order": 2, "kron_stage_qubit": -1},
+    "order_scatter": {"kron_order": 3},
 }
 
 
@@ -75,7 +78,7 @@ def ctx():
 @pytest.mark.parametrize("knobs", list(_KNOBS), ids=list(_KNOBS))
 def test_kron_variants_match_oracle(cases, ctx, knobs):
     t = D.get_tuning(ctx)
-    t.update(kron_split=0, kron_stage_qubit=0, kron_nontemporal=0)
+    t.update(kron_split=0, kron_stage_qubit=0, kron_nontemporal=0, kron_order=0)
     t.update(_KNOBS[knobs])
     D.set_tuning(ctx, **t)
     for name, n, gates, x, ref in cases:
@@ -93,6 +96,6 @@ def test_kron_variants_match_oracle(cases, ctx, knobs):
 
 
 def test_kron_knobs_rejected_out_of_range(ctx):
-    for bad in ({"kron_split": 7}, {"kron_stage_qubit": 7}, {"kron_nontemporal": 2}):
+    for bad in ({"kron_split": 7}, {"kron_stage_qubit": 7}, {"kron_nontemporal": 2}, {"kron_order": 4}):
         with pytest.raises(D.DiaqError):
             D.set_tuning(ctx, **bad)
