@@ -620,6 +620,7 @@ def qft_extra(D, W, torch, ctx):
         g.manual_seed(seed)
         for kw in ({}, {"fuse": True, "max_fused_qubits": 2}, {"kron": True},
                    {"kron": True, "fuse": True, "max_fused_qubits": 3},
+                   {"kron": True, "fuse": True, "max_fused_qubits": 4},
                    {"kron": True, "fuse": True, "max_fused_qubits": 5}):
             plan = D.make_plan(**kw) if kw else None
             nops, nbytes = D.plan_count(gates, n, plan)

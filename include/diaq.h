@@ -460,7 +460,10 @@ typedef struct diaq_tuning {
                               interleaved), 1 each XCD a contiguous eighth,
                               2 the two halves interleaved, 3 blocks
                               scattered by an odd multiplier */
-  int32_t kron_reserved;
+  int32_t spmv_order;      /* tile order of the product kernel where neither
+                              XCD runs nor partner alternation apply: 0 launch
+                              order, 1 each XCD a contiguous eighth of the
+                              tiles, 2 the two halves interleaved */
 } diaq_tuning_t;
 
 diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);
@@ -485,7 +488,8 @@ typedef struct diaq_spmv_shape {
                               consecutive tiles */
   int32_t pair_bit;        /* > 0: each XCD alternates between tiles that
                               differ in this tile-index bit */
-  int32_t reserved;
+  int32_t tile_order;      /* otherwise: 0 launch order, 1 XCD-contiguous
+                              eighths, 2 halves interleaved */
   int64_t blocks;          /* workgroups of the launch */
 } diaq_spmv_shape_t;
 diaq_status_t diaq_spmv_shape(const diaq_gate_t* gate, int32_t nqubits, diaq_dtype_t dtype,

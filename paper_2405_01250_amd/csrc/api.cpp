@@ -276,6 +276,7 @@ static diaq_status_t check_tuning(const diaq_tuning_t* t) {
   if (t->kron_small_qubits < -1 || t->kron_small_qubits > 14)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_small_qubits must be in [-1, 14]");
   if (t->kron_order < 0 || t->kron_order > 3) return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_order must be 0..3");
+  if (t->spmv_order < 0 || t->spmv_order > 2) return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_order must be 0, 1 or 2");
   return DIAQ_OK;
 }
 

@@ -160,6 +160,7 @@ void keep_other_knobs(const diaq_tuning_t& cur, diaq_tuning_t* best) {
   best->kron_nontemporal = cur.kron_nontemporal;
   best->kron_small_qubits = cur.kron_small_qubits;
   best->kron_order = cur.kron_order;
+  best->spmv_order = cur.spmv_order;
 }
 
 }  // namespace
@@ -389,7 +390,7 @@ diaq_status_t diaq_autotune_plan(diaq_ctx_t ctx, const diaq_gate_t* gates, int64
       int64_t nops = 0;
       if (kron && fuse && k > 3) {
         std::vector<BigOp> big;
-        DIAQ_TRY(plan_big(gates, ngates, n, k, &big));
+        DIAQ_TRY(plan_big(gates, ngates, n, k, &big, dtype));
         nops = int64_t(big.size());
         bytes = double(nops) * 2.0 * s * N;
         cands.push_back(Cand{p, bytes / (rate_kron * 1e6) + double(nops) * launch_ms, 0.0});

@@ -236,7 +236,7 @@ diaq_status_t apply_range(diaq_ctx* ctx, const diaq_gate_t* gates, int64_t begin
   } else if (plan && plan->kron && plan->fuse && kmax > 3) {
     // groups of four or five qubits: dense local matrices
     std::vector<BigOp> ops;
-    st = plan_big(gates + begin, end - begin, nqubits, kmax, &ops);
+    st = plan_big(gates + begin, end - begin, nqubits, kmax, &ops, dtype);
     if (st == DIAQ_OK) st = run_big(ctx, ops, nqubits, dtype, state);
     res = state;
   } else if (plan && plan->kron) {
@@ -305,7 +305,7 @@ diaq_status_t diaq_plan_count(const diaq_gate_t* gates, int64_t ngates, int32_t 
     int64_t count = 0;
     if (plan && plan->kron && plan->fuse && plan->max_fused_qubits > 3) {
       std::vector<BigOp> ops;
-      DIAQ_TRY(plan_big(gates, ngates, nqubits, plan->max_fused_qubits, &ops));
+      DIAQ_TRY(plan_big(gates, ngates, nqubits, plan->max_fused_qubits, &ops, dtype));
       count = int64_t(ops.size());
       b = double(count) * 2.0 * s * N;  // every operation reads and writes the state once
     } else if (plan && plan->kron) {
@@ -383,7 +383,7 @@ diaq_status_t diaq_adjoint_grad(diaq_ctx_t ctx, const diaq_gate_t* gates, int64_
       const int kmax = plan->max_fused_qubits > 0 ? plan->max_fused_qubits : 4;
       if (kmax > 3) {
         std::vector<BigOp> ops;
-        DIAQ_TRY(plan_big(gates, ngates, nqubits, kmax, &ops));
+        DIAQ_TRY(plan_big(gates, ngates, nqubits, kmax, &ops, dtype));
         DIAQ_TRY(run_big(ctx, ops, nqubits, dtype, psi));
       } else {
         std::vector<FusedOp> ops;

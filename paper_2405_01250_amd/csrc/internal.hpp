@@ -186,12 +186,12 @@ struct TableHead {
   int32_t nq;       // qubits of the table
   int32_t nruns;    // runs of consecutive qubits; none crosses bit 32
   int32_t run[10];  // first qubit | length << 8 | first index bit << 16
-  int32_t roff[8];  // index bits of the operation's row offsets off[r]
+  uint8_t roff[32]; // index bits of the operation's row offsets off[r]
 };
 static_assert(sizeof(TableHead) == 80, "table header is 80 bytes");
 inline size_t table_bytes(int nq) { return sizeof(TableHead) + (size_t(16) << nq); }
 // Appends the tables of f[0..nf) to *out (planner.cpp); returns how many.
-// With row offsets off[0..noff) (noff <= 8; the element offsets of an
+// With row offsets off[0..noff) (noff <= 32; the element offsets of an
 // operation's local rows, on bits its cosets leave 0), each header also
 // holds roff[r] = the table index bits of off[r].
 int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out, const int64_t* off = nullptr,
@@ -225,14 +225,14 @@ __device__ __forceinline__ void apply_tables(const char* tabs, int nt, uint64_t 
   }
 }
 
-// Rows base | off[r], r < D, of a coset whose tables were compiled with
-// those row offsets: (vr[r], vi[r]) *= the product of the nt tables.  A
-// table's header is decoded once for all D rows: the coset's index bits
-// come from base, each row ORs in the header's roff[r] (the bit gather is
-// linear over disjoint bits).
+// Rows base | off[r0 + r], r < D, of a coset whose tables were compiled
+// with those row offsets: (vr[r], vi[r]) *= the product of the nt tables.
+// A table's header is decoded once for all D rows: the coset's index bits
+// come from base, each row ORs in the header's roff[r0 + r] (the bit
+// gather is linear over disjoint bits).
 template <int D>
 __device__ __forceinline__ void apply_tables_rows(const char* tabs, int nt, uint64_t base, double (&vr)[D],
-                                                  double (&vi)[D]) {
+                                                  double (&vi)[D], int r0 = 0) {
   typedef __attribute__((address_space(4))) const char GChar;
   typedef __attribute__((address_space(4))) const TableHead GHead;
   typedef __attribute__((address_space(4))) const double GDouble;
@@ -251,7 +251,7 @@ __device__ __forceinline__ void apply_tables_rows(const char* tabs, int nt, uint
     GDouble* e = (GDouble*)(p + sizeof(TableHead));
 #pragma unroll
     for (int r = 0; r < D; r++) {
-      const uint32_t ir = idx | uint32_t(h->roff[r]);
+      const uint32_t ir = idx | uint32_t(h->roff[r0 + r]);
       const double fr = e[2 * ir], fi = e[2 * ir + 1];
       const double nr2 = vr[r] * fr - vi[r] * fi;
       vi[r] = vr[r] * fi + vi[r] * fr;
@@ -305,7 +305,11 @@ struct BigOp {
   bool raw = false;
   LocalGate lg;
 };
-diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops);
+// With kmax = 5 the grouping with a limit of 3, 4 or 5 qubits of least
+// modelled time is kept (a dense five-qubit group costs more than a pass
+// over the state; dt sets the ratio).
+diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops,
+                       diaq_dtype_t dt = DIAQ_C128);
 // Applies the operations in place (each one read and one write of the
 // state), with profiling intervals of 2 s N bytes per operation.
 diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_dtype_t dt, void* state);

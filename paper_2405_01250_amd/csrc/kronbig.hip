@@ -381,7 +381,8 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_lds_kernel(LdsArgs a, 
   }
 }
 
-// Dense groups with the rows split over the waves of a block.  The block
+// Dense groups with the rows split over the waves of a block (factor tables
+// compiled with the group's 2^K row offsets).  The block
 // stages 64 cosets in LDS exactly as kron_lds_kernel does; wave p then forms
 // rows [p L, (p + 1) L) of every coset, taking the coset's 2^K inputs out of
 // LDS one at a time, so a lane holds only its L output rows (not the 2^K
@@ -472,12 +473,11 @@ __global__ __launch_bounds__(kLdsLanes * PARTS) void kron_split_kernel(LdsArgs a
   }
   // every wave has read its inputs before any output overwrites them
   __syncthreads();
+  // the table headers carry the index bits of the 2^K row offsets, so each
+  // table is decoded once for the lane's L rows
+  if (a.nt) apply_tables_rows<L>(a.tabs, a.nt, uint64_t(base + lo), ar, ai, r0);
 #pragma unroll
-  for (int rr = 0; rr < L; rr++) {
-    double yr = ar[rr], yi = ai[rr];
-    if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(base + lo + a.roff[r0 + rr]), yr, yi);
-    sx[slot(a, el + a.eoff[r0 + rr])] = double2{yr, yi};
-  }
+  for (int rr = 0; rr < L; rr++) sx[slot(a, el + a.eoff[r0 + rr])] = double2{ar[rr], ai[rr]};
   __syncthreads();
   {
     double2 t[L];
@@ -740,8 +740,9 @@ diaq_status_t launch_staged(diaq_ctx* ctx, const int* S, int k, const double* dm
   return DIAQ_OK;
 }
 
-diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops) {
-  if (kmax < 1 || kmax > 5) return fail(DIAQ_ERR_INVALID_ARGUMENT, "max_fused_qubits must be 1..5");
+namespace {
+
+diaq_status_t plan_big_greedy(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops) {
   ops->clear();
   for (int64_t gi = 0; gi < ngates; gi++) {
     LocalGate lg;
@@ -814,6 +815,43 @@ diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax
   return DIAQ_OK;
 }
 
+// Modelled time of a plan in units of one pass over the state: an operation
+// of at most four qubits costs its memory pass; a dense five-qubit group's
+// 4096 FMAs per coset take longer than that pass (n = 28: 1.85 against
+// 1.44 ms in complex128; in complex64, whose pass is half as long, 1.45
+// against 0.67 ms).
+double plan_cost(const std::vector<BigOp>& ops, diaq_dtype_t dt) {
+  const double five = dt == DIAQ_C128 ? 1.3 : 2.2;
+  double c = 0;
+  for (const BigOp& op : ops) c += (!op.raw && op.k == 5) ? five : 1.0;
+  return c;
+}
+
+}  // namespace
+
+diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax, std::vector<BigOp>* ops,
+                       diaq_dtype_t dt) {
+  if (kmax < 1 || kmax > 5) return fail(DIAQ_ERR_INVALID_ARGUMENT, "max_fused_qubits must be 1..5");
+  DIAQ_TRY(plan_big_greedy(gates, ngates, n, kmax, ops));
+  // groups of up to five qubits: the greedy grouping with a narrower limit
+  // can be cheaper (fewer five-qubit groups for few operations saved);
+  // keep the plan of least modelled time (QFT-29: 24 operations with five
+  // qubits against 25 with three, 97 against 81 ms)
+  if (kmax == 5) {
+    double best = plan_cost(*ops, dt);
+    for (int k : {4, 3}) {
+      std::vector<BigOp> alt;
+      DIAQ_TRY(plan_big_greedy(gates, ngates, n, k, &alt));
+      const double c = plan_cost(alt, dt);
+      if (c < best) {
+        best = c;
+        ops->swap(alt);
+      }
+    }
+  }
+  return DIAQ_OK;
+}
+
 diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_dtype_t dt, void* state) {
   const int64_t N = int64_t(1) << n;
   // one table: every operation's matrix (2 D^2 doubles), then the factors
@@ -845,7 +883,14 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
       const std::vector<double> lm = mfma_operands(ops[k].m, ops[k].k);
       mats.insert(mats.end(), lm.begin(), lm.end());
     }
-    tabs.add(ops[k].post);
+    // headers with the index bits of the operation's 2^k row offsets, for
+    // kernels that decode each table once per coset
+    int64_t off[32] = {0};
+    const int nrows = ops[k].raw ? 0 : (1 << ops[k].k);
+    for (int r = 0; r < nrows; r++)
+      for (int j = 0; j < ops[k].k; j++)
+        if ((r >> j) & 1) off[r] |= int64_t(1) << ops[k].q[j];
+    tabs.add(ops[k].post, nrows ? off : nullptr, nrows);
   }
   const size_t mb = ((mats.size() * sizeof(double) + 255) / 256) * 256;
   const size_t bytes = mb + tabs.bytes.size() + 256;

@@ -190,9 +190,9 @@ int compile_factors(const DiagFactor* f, int nf, std::vector<char>* out, const i
       h.run[h.nruns++] = Q[i] | ((e - i + 1) << 8) | (i << 16);
       i = e + 1;
     }
-    for (int r = 0; r < noff && r < 8; r++)
+    for (int r = 0; r < noff && r < 32; r++)
       for (int j = 0; j < nq; j++)
-        if ((uint64_t(off[r]) >> Q[j]) & 1) h.roff[r] |= 1 << j;
+        if ((uint64_t(off[r]) >> Q[j]) & 1) h.roff[r] = uint8_t(h.roff[r] | (1u << j));
     const size_t at = out->size();
     out->resize(at + table_bytes(nq));
     std::memcpy(out->data() + at, &h, sizeof(h));

@@ -59,6 +59,7 @@ struct RowMap {
   int32_t gbit[3];    // ascending qubit indices, each >= tile_log2
   int32_t run_log2;   // XCD runs of 2^run_log2 tiles (0: launch order)
   int32_t pair_bit;   // > 0: each XCD alternates between tiles differing in this tile bit
+  int32_t order;      // otherwise: 1 XCD-contiguous eighths, 2 halves interleaved
 };
 
 // Tile of workgroup b.  The device hands consecutive workgroups to its 8
@@ -78,7 +79,12 @@ __device__ __forceinline__ int64_t tile_of(int64_t b, const RowMap& m) {
     const int p = m.pair_bit;
     return ((c >> p) << (p + 1)) | ((u & 1) << p) | (c & ((int64_t(1) << p) - 1));
   }
-  if (m.run_log2 == 0) return b;
+  if (m.run_log2 == 0) {
+    const int64_t nb = int64_t(gridDim.x);
+    if (m.order == 1 && (nb & 7) == 0) return (b & 7) * (nb >> 3) + (b >> 3);
+    if (m.order == 2 && (nb & 1) == 0) return (b >> 1) + (b & 1) * (nb >> 1);
+    return b;
+  }
   const int64_t w = int64_t(1) << m.run_log2, chunk = 8 * w;
   if (b >= (int64_t(gridDim.x) / chunk) * chunk) return b;
   const int64_t in = b % chunk;
@@ -518,6 +524,7 @@ Plan plan_rows(const SpmvOp& op, const diaq_tuning_t& t, int rpt_override) {
         (tile_bytes << pb) >= kPairOrderMinBytes)
       p.map.pair_bit = pb;
   }
+  if (p.map.run_log2 == 0 && p.map.pair_bit == 0) p.map.order = t.spmv_order;
   return p;
 }
 
@@ -660,6 +667,7 @@ diaq_status_t spmv_shape(const SpmvOp& op, const diaq_tuning_t& t, diaq_spmv_sha
   for (int b = 0; b < p.map.ng; b++) out->group_qubits[b] = p.map.gbit[b];
   out->xcd_run_log2 = p.map.run_log2;
   out->pair_bit = p.map.pair_bit;
+  out->tile_order = p.map.order;
   out->blocks = p.blocks;
   return DIAQ_OK;
 }

@@ -261,6 +261,11 @@ def test_spmv_shape_host_only(lib):
     assert (s["group"], s["xcd_run_log2"]) == (1, 2)
     s = D.spmv_shape(W.Gate("RZ", (5,), (), (0.3,)), 28)
     assert s["in_place"] == 1
+    # tile orders apply where neither XCD runs nor partner alternation do
+    s = D.spmv_shape(W.u3(0.1, 0.2, 0.3, 14), 28, spmv_order=2, spmv_group_bits=-1)
+    assert (s["xcd_run_log2"], s["pair_bit"], s["tile_order"]) == (0, 0, 2)
+    s = D.spmv_shape(W.u3(0.1, 0.2, 0.3, 9), 28, spmv_order=2)
+    assert (s["xcd_run_log2"], s["tile_order"]) == (2, 0)
     with pytest.raises(D.DiaqError):
         D.spmv_shape(W.u3(0.1, 0.2, 0.3, 28), 28)
     with pytest.raises(D.DiaqError):

@@ -2,7 +2,8 @@
 ownership), forced through the tuning knobs: rows per lane 1, 2, 4; one or
 three diagonals per chunk; non-temporal value / y streams on and off; tile
 groups of G = 1, 2, 4, 8 over the coupling qubits (by threshold and by
-per-qubit mask); XCD-aware tile orders on and off.  Each variant only
+per-qubit mask); XCD-aware tile orders on and off, XCD-contiguous and
+interleaved-halves tile orders.  Each variant only
 changes which lane computes a row and in which order tiles run, never the
 arithmetic of a row (ascending diagonals, the same fused multiply-adds), so
 every variant must equal the default one bit for bit, and the default must
@@ -68,7 +69,7 @@ def restore_tuning():
 
 
 _DEFAULT = dict(spmv_rows=0, spmv_group_bits=0, spmv_chunk=0, spmv_nontemporal=0, spmv_group_min_qubit=0,
-                spmv_xcd_runs=0, spmv_group_qubits=0)
+                spmv_xcd_runs=0, spmv_group_qubits=0, spmv_order=0)
 
 # tile grouping: none; G up to 8 over coupling qubits >= 18; G <= 2; G <= 4;
 # per-qubit mask (qubits 19 and 21)
@@ -98,8 +99,10 @@ def test_spmv_variants_bitwise_and_oracle(case, restore_tuning, dtype, rows):
     tol = 1e-12 if dtype == torch.complex128 else 1e-5
     base = _run(ctx, gates, x0, n, dtype, None)
     assert_state_close(base, ref, tol, "default knobs", l2tol=tol if dtype == torch.complex128 else 1e-4)
-    for chunk, nt, (gname, grouping), xcd in itertools.product((1, 3), (0, -1), _GROUPINGS.items(), (0, -1)):
-        knobs = dict(spmv_rows=rows, spmv_chunk=chunk, spmv_nontemporal=nt, spmv_xcd_runs=xcd, **grouping)
+    for chunk, nt, (gname, grouping), (xcd, order) in itertools.product((1, 3), (0, -1), _GROUPINGS.items(),
+                                                                         ((0, 0), (-1, 0), (0, 1), (0, 2))):
+        knobs = dict(spmv_rows=rows, spmv_chunk=chunk, spmv_nontemporal=nt, spmv_xcd_runs=xcd, spmv_order=order,
+                     **grouping)
         got = _run(ctx, gates, x0, n, dtype, None, **knobs)
         assert np.array_equal(got, base), knobs
 
