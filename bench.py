@@ -40,7 +40,7 @@ def _args():
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--seed", type=int, default=28)
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--extras", type=int, default=1, help="also time adjoint vs parameter shift (HEA n=20)")
     ap.add_argument("--tune-cache", default=None,
@@ -152,6 +152,30 @@ def cpu_baseline(n, gates, budget_s, s_bytes, repeats=3):
     orc.set_threads(1)
     one = stats([sample(max(1.0, budget_s / (3 * repeats))) for _ in range(repeats)])
     orc.set_threads(cores)
+    # the other workload shapes, whole circuits, two runs each (bounded:
+    # GHZ-28 is 28 gates, QFT-24 312 gates on 2^24 amplitudes, and 8
+    # circuits of the QAOA batch)
+    others = {}
+    for name, nn, gl, x0f in (("ghz28", 28, W.ghz(28), lambda: W.zero_state(28)),
+                              ("qft24", 24, W.qft(24), lambda: W.random_state(24, 24))):
+        runs = []
+        for _ in range(2):
+            psi = x0f()
+            t0 = time.perf_counter()
+            orc.apply_circuit(psi, nn, gl, copy=False)
+            runs.append(time.perf_counter() - t0)
+        r = np.array(runs)
+        others[name] = {"gates": len(gl), "s": round(float(r.mean()), 4), "s_std": round(float(r.std()), 4),
+                        "gates_per_s": round(len(gl) / float(r.mean()), 2),
+                        "GBps": round(len(gl) * 2.0 * (1 << nn) * s_bytes / float(r.mean()) / 1e9, 2)}
+        del psi
+    insts = W.qaoa_batch(512, 512)[:8]
+    t0 = time.perf_counter()
+    for inst in insts:
+        orc.energy(W.zero_state(inst.n), inst.n, inst.gates, inst.terms)
+    dq = time.perf_counter() - t0
+    others["qaoa_batch_sample"] = {"circuits": len(insts), "s": round(dq, 3), "circuits_per_s": round(len(insts) / dq, 2),
+                                   "what": "energies (no gradients) of the first 8 circuits of the 512-circuit batch"}
     # gradient baseline: parameter shift needs 2 energies per occurrence
     hn, layers = 20, 8
     hg, theta, terms = W.hea(hn, layers, 20)
@@ -179,6 +203,7 @@ def cpu_baseline(n, gates, budget_s, s_bytes, repeats=3):
                           "gates/s x 2 N s (the oracle's in-place read + write of the state); mean and std over "
                           "the runs" % (repeats, budget_s / repeats, n),
                 "one_core": one,
+                "workloads": others,
                 "hea20_param_shift": {"energy_s": round(e_s, 3), "shifted_energies": 2 * len(theta),
                                       "grads_per_s": round(1.0 / (2 * len(theta) * e_s), 5),
                                       "sample": "%d energies of the HEA n=20 circuit (480 gates) timed on all "
