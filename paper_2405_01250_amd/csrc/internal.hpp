@@ -459,8 +459,8 @@ struct SegmentPlan {
 };
 
 constexpr int kSegMaxDots = 64;
-constexpr int kSegLdsGates = 128;   // SegGate entries of one segment (staged in LDS)
-constexpr int kSegLdsPool = 2048;   // matrix doubles of one segment (staged in LDS)
+constexpr int kSegLdsGates = 128;   // SegGate entries of one segment
+constexpr int kSegLdsPool = 2048;   // matrix doubles of one segment (its diagonal tables are staged in LDS)
 
 // Cut the reverse sweep (or, with forward, the circuit in its own order)
 // into segments: consecutive gates whose non-diagonal targets fit in 3

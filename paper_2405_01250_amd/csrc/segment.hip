@@ -41,7 +41,7 @@ struct SegArgs {
   int32_t sorted[3];   // S ascending
   int32_t ngates;
   int32_t ndots;
-  int32_t pad;
+  int32_t tables;      // 1: diagonal gates, whose tables are staged in LDS
   int64_t off[8];      // global offset of local index r
   const SegGate* gates;
   const double* pool;
@@ -64,11 +64,37 @@ struct Coset {
   double pr[8], pi[8], lr[8], li[8];
 };
 
+// The segment's gate list and matrices are read where the host (or the
+// batch's angle refresh, an earlier kernel) wrote them, through the
+// constant address space: every lane reads the same gate and the same
+// matrix entries, so these become scalar loads whose values feed the FMAs
+// from SGPRs (staging them in LDS made each entry a 64-lane LDS read, as
+// much LDS traffic per coset as the state moves to HBM).  The per-row
+// entries of diagonal tables differ by lane and stay vector loads.
+typedef __attribute__((address_space(4))) const double CD;
+typedef __attribute__((address_space(4))) const SegGate CG;
+
+// Gate i of the list, field by field through the constant address space.
+__device__ __forceinline__ SegGate seg_gate(const SegGate* gates, int i) {
+  CG* p = (CG*)(gates) + i;
+  SegGate g;
+  g.kind = p->kind;
+  g.b0 = p->b0;
+  g.b1 = p->b1;
+  g.dot = p->dot;
+  g.dk = p->dk;
+  g.q[0] = p->q[0];
+  g.q[1] = p->q[1];
+  g.q[2] = p->q[2];
+  g.cmask = p->cmask;
+  g.moff = p->moff;
+  return g;
+}
+
 // y = M x on the local indices idx[0..D) of the coset, for psi and lambda,
 // after the dot conj(lambda) (G psi) when G != nullptr.
-template <int D, bool LAM>
-__device__ __forceinline__ void local_apply(Coset& s, const int (&idx)[D], const double* __restrict__ m,
-                                            const double* __restrict__ g, double& dre, double& dim) {
+template <int D, bool LAM, typename P>
+__device__ __forceinline__ void local_apply(Coset& s, const int (&idx)[D], P m, P g, double& dre, double& dim) {
   if (LAM && g) {
 #pragma unroll
     for (int r = 0; r < D; r++) {
@@ -115,14 +141,12 @@ __device__ __forceinline__ void local_apply(Coset& s, const int (&idx)[D], const
 
 // One-target gate on local bit B: four pairs (r, r | 1 << B).
 template <int B, bool LAM>
-__device__ __forceinline__ void apply_one(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
-                                          double& dim) {
-  const double* m = a.pool + sg.moff;
-  const double* g = sg.dot >= 0 ? m + 8 : nullptr;
+__device__ __forceinline__ void apply_one(Coset& s, const SegArgs& a, const double* pool, const SegGate& sg, int64_t base,
+                                          double& dre, double& dim) {
+  CD* m = (CD*)(pool + sg.moff);
+  CD* g = sg.dot >= 0 ? m + 8 : nullptr;
 #pragma unroll
   for (int p = 0; p < 4; p++) {
-    // re-read the matrix from LDS for every pair rather than keep it in registers
-    __asm__ volatile("" ::: "memory");
     const int r0 = ((p >> B) << (B + 1)) | (p & ((1 << B) - 1));
     const int idx[2] = {r0, r0 | (1 << B)};
     if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
@@ -132,14 +156,13 @@ __device__ __forceinline__ void apply_one(Coset& s, const SegArgs& a, const SegG
 
 // Two-target gate: target 0 on local bit B0, target 1 on B1; two quads.
 template <int B0, int B1, bool LAM>
-__device__ __forceinline__ void apply_two(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
-                                          double& dim) {
+__device__ __forceinline__ void apply_two(Coset& s, const SegArgs& a, const double* pool, const SegGate& sg, int64_t base,
+                                          double& dre, double& dim) {
   constexpr int FREE = 7 & ~((1 << B0) | (1 << B1));
-  const double* m = a.pool + sg.moff;
-  const double* g = sg.dot >= 0 ? m + 32 : nullptr;
+  CD* m = (CD*)(pool + sg.moff);
+  CD* g = sg.dot >= 0 ? m + 32 : nullptr;
 #pragma unroll
   for (int p = 0; p < 2; p++) {
-    __asm__ volatile("" ::: "memory");
     const int r0 = p ? FREE : 0;
     const int idx[4] = {r0, r0 | (1 << B0), r0 | (1 << B1), r0 | (1 << B0) | (1 << B1)};
     if (sg.cmask && ((uint64_t(base + a.off[r0]) & sg.cmask) != sg.cmask)) continue;
@@ -148,11 +171,11 @@ __device__ __forceinline__ void apply_two(Coset& s, const SegArgs& a, const SegG
 }
 
 template <bool LAM>
-__device__ __forceinline__ void apply_three(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base,
-                                            double& dre, double& dim) {
+__device__ __forceinline__ void apply_three(Coset& s, const double* pool, const SegGate& sg, int64_t base, double& dre,
+                                            double& dim) {
   if (sg.cmask && ((uint64_t(base) & sg.cmask) != sg.cmask)) return;
-  const double* m = a.pool + sg.moff;
-  const double* g = sg.dot >= 0 ? m + 128 : nullptr;
+  CD* m = (CD*)(pool + sg.moff);
+  CD* g = sg.dot >= 0 ? m + 128 : nullptr;
   const int idx[8] = {0, 1, 2, 3, 4, 5, 6, 7};
   local_apply<8, LAM>(s, idx, m, g, dre, dim);
 }
@@ -160,9 +183,9 @@ __device__ __forceinline__ void apply_three(Coset& s, const SegArgs& a, const Se
 // Diagonal gate on any qubits: each amplitude reads its entry of the
 // gate's (at most 8-entry) table.
 template <bool LAM>
-__device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const SegGate& sg, int64_t base, double& dre,
-                                           double& dim) {
-  const double* v = a.pool + sg.moff;
+__device__ __forceinline__ void apply_diag(Coset& s, const SegArgs& a, const double* tabs, const SegGate& sg,
+                                           int64_t base, double& dre, double& dim) {
+  const double* v = tabs + sg.moff;
   const double* g = v + 2 * (1 << sg.dk);
 #pragma unroll
   for (int r = 0; r < 8; r++) {
@@ -207,8 +230,8 @@ __device__ __forceinline__ void flush_dot(double2 (*acc)[kSegBlock / 64], int j,
 // Consecutive members that share a dot slot (same parameter and scale) add
 // into one dot.
 template <bool LAM>
-__device__ __forceinline__ void apply_run(Coset& s, const SegArgs& a, int gi, int m, int64_t base,
-                                          double2 (*acc)[kSegBlock / 64]) {
+__device__ __forceinline__ void apply_run(Coset& s, const SegArgs& a, const SegGate* gates, const double* tabs, int gi, int m,
+                                          int64_t base, double2 (*acc)[kSegBlock / 64]) {
   double fr[8], fi[8];
 #pragma unroll
   for (int r = 0; r < 8; r++) {
@@ -218,13 +241,13 @@ __device__ __forceinline__ void apply_run(Coset& s, const SegArgs& a, int gi, in
   int cur = -1;
   double dre = 0, dim = 0;
   for (int k = 1; k <= m; k++) {
-    const SegGate mg = a.gates[gi + k];
+    const SegGate mg = seg_gate(gates, gi + k);
     if (LAM && mg.dot >= 0 && mg.dot != cur) {
       if (cur >= 0) flush_dot(acc, cur, dre, dim);
       cur = mg.dot;
       dre = dim = 0;
     }
-    const double* vt = a.pool + mg.moff;
+    const double* vt = tabs + mg.moff;
     const double* gt = vt + 2 * (1 << mg.dk);
 #pragma unroll
     for (int r = 0; r < 8; r++) {
@@ -272,22 +295,13 @@ __device__ __forceinline__ void segment_body(const SegArgs& ga, typename Vec<R>:
   auto* __restrict__ lam = gptr(reinterpret_cast<NV*>(lam_in));
   auto* __restrict__ partial = gptr(reinterpret_cast<ND*>(partial_in));
   __shared__ double2 acc[kSegMaxDots][kSegWaves];
-  // the segment's gate list and matrices, staged in LDS: every lane reads
-  // the same entries, gate after gate
-  __shared__ SegGate lgates[kSegLdsGates];
+  // the tables of diagonal gates, staged in LDS (their entries differ by
+  // lane); dense matrices and the gate list are read through scalar loads
   __shared__ double lpool[kSegLdsPool];
-  {
-    const int words = ga.ngates * int(sizeof(SegGate) / sizeof(uint64_t));
-    const auto* src = gptr(reinterpret_cast<const uint64_t*>(ga.gates));
-    uint64_t* dst = reinterpret_cast<uint64_t*>(lgates);
-    for (int t = threadIdx.x; t < words; t += kSegBlock) dst[t] = src[t];
-    const auto* pool = gptr(ga.pool);
-    for (int t = threadIdx.x; t < int(ga.pool_n); t += kSegBlock) lpool[t] = pool[ga.pool_lo + t];
-  }
-  SegArgs a = ga;
-  a.gates = lgates;
-  a.pool = lpool - ga.pool_lo;
-  __syncthreads();
+  const SegArgs& a = ga;
+  const SegGate* gates = ga.gates;
+  const double* pool = ga.pool;
+  const double* tabs = lpool - ga.pool_lo;
   const int64_t c = block * kSegBlock + threadIdx.x;
   const bool live = c < a.ncos;
   int64_t base = 0;
@@ -299,6 +313,7 @@ __device__ __forceinline__ void segment_body(const SegArgs& ga, typename Vec<R>:
       base = (base & ((int64_t(1) << p) - 1)) | ((base >> p) << (p + 1));
     }
   }
+  // the state loads go out first; the staging below overlaps their latency
   Coset s;
 #pragma unroll
   for (int r = 0; r < 8; r++) {
@@ -309,10 +324,15 @@ __device__ __forceinline__ void segment_body(const SegArgs& ga, typename Vec<R>:
     s.lr[r] = double(y.x);
     s.li[r] = double(y.y);
   }
+  if (ga.tables) {
+    const auto* src = gptr(ga.pool);
+    for (int t = threadIdx.x; t < int(ga.pool_n); t += kSegBlock) lpool[t] = src[ga.pool_lo + t];
+    __syncthreads();
+  }
   for (int gi = 0; gi < a.ngates; gi++) {
-    const SegGate sg = a.gates[gi];
+    const SegGate sg = seg_gate(gates, gi);
     if (sg.kind == kRun) {
-      apply_run<LAM>(s, a, gi, sg.b0, base, acc);
+      apply_run<LAM>(s, a, gates, tabs, gi, sg.b0, base, acc);
       gi += sg.b0;
       continue;
     }
@@ -320,27 +340,27 @@ __device__ __forceinline__ void segment_body(const SegArgs& ga, typename Vec<R>:
     if (live) {
       switch (sg.kind) {
         case kOne:
-          if (sg.b0 == 0) apply_one<0, LAM>(s, a, sg, base, dre, dim);
-          else if (sg.b0 == 1) apply_one<1, LAM>(s, a, sg, base, dre, dim);
-          else apply_one<2, LAM>(s, a, sg, base, dre, dim);
+          if (sg.b0 == 0) apply_one<0, LAM>(s, a, pool, sg, base, dre, dim);
+          else if (sg.b0 == 1) apply_one<1, LAM>(s, a, pool, sg, base, dre, dim);
+          else apply_one<2, LAM>(s, a, pool, sg, base, dre, dim);
           break;
         case kTwo: {
           const int code = sg.b0 * 3 + sg.b1;
           switch (code) {
-            case 1: apply_two<0, 1, LAM>(s, a, sg, base, dre, dim); break;
-            case 2: apply_two<0, 2, LAM>(s, a, sg, base, dre, dim); break;
-            case 3: apply_two<1, 0, LAM>(s, a, sg, base, dre, dim); break;
-            case 5: apply_two<1, 2, LAM>(s, a, sg, base, dre, dim); break;
-            case 6: apply_two<2, 0, LAM>(s, a, sg, base, dre, dim); break;
-            default: apply_two<2, 1, LAM>(s, a, sg, base, dre, dim); break;
+            case 1: apply_two<0, 1, LAM>(s, a, pool, sg, base, dre, dim); break;
+            case 2: apply_two<0, 2, LAM>(s, a, pool, sg, base, dre, dim); break;
+            case 3: apply_two<1, 0, LAM>(s, a, pool, sg, base, dre, dim); break;
+            case 5: apply_two<1, 2, LAM>(s, a, pool, sg, base, dre, dim); break;
+            case 6: apply_two<2, 0, LAM>(s, a, pool, sg, base, dre, dim); break;
+            default: apply_two<2, 1, LAM>(s, a, pool, sg, base, dre, dim); break;
           }
           break;
         }
         case kThree:
-          if constexpr (T3) apply_three<LAM>(s, a, sg, base, dre, dim);
+          if constexpr (T3) apply_three<LAM>(s, pool, sg, base, dre, dim);
           break;
         default:
-          apply_diag<LAM>(s, a, sg, base, dre, dim);
+          apply_diag<LAM>(s, a, tabs, sg, base, dre, dim);
           break;
       }
     }
@@ -484,7 +504,7 @@ __global__ __launch_bounds__(256) void grouped_reduce_kernel(const GroupRed* __r
   }
 }
 
-SegArgs make_seg_args(const Segment& seg, int n, const SegGate* dg, const double* dp) {
+SegArgs make_seg_args(const SegmentPlan& P, const Segment& seg, int n, const SegGate* dg, const double* dp) {
   SegArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ncos = (int64_t(1) << n) >> 3;
@@ -501,6 +521,10 @@ SegArgs make_seg_args(const Segment& seg, int n, const SegGate* dg, const double
   a.pool = dp;
   a.pool_lo = seg.pool_lo;
   a.pool_n = seg.pool_n;
+  for (int64_t g = 0; g < seg.ngates; g++) {
+    const int32_t k = P.gates[size_t(seg.first + g)].kind;
+    if (k == kDiag || k == kRun || k == kRunMember) a.tables = 1;
+  }
   return a;
 }
 
@@ -711,7 +735,7 @@ diaq_status_t run_segments(diaq_ctx* ctx, hipStream_t stream, const SegmentPlan&
   const int64_t blocks = segment_blocks(n);
   int64_t row = 0, ndots = 0, nred = 0;
   for (const Segment& seg : P.segs) {
-    const SegArgs a = make_seg_args(seg, n, dg, dp);
+    const SegArgs a = make_seg_args(P, seg, n, dg, dp);
     double2* part = partial + row;
     if (dt == DIAQ_C128) {
       if (seg.three) launch_segment<double, true>(P.forward, blocks, stream, a, psi, lam, part);
@@ -820,7 +844,7 @@ diaq_status_t build_grouped(const std::vector<GroupItem>& items, bool forward, G
       const size_t pb = ((P.pool.size() * sizeof(double) + 255) / 256) * 256;
       GroupSeg g;
       std::memset(&g, 0, sizeof(g));
-      g.a = make_seg_args(seg, it.n, reinterpret_cast<const SegGate*>(t), reinterpret_cast<const double*>(t + gb));
+      g.a = make_seg_args(P, seg, it.n, reinterpret_cast<const SegGate*>(t), reinterpret_cast<const double*>(t + gb));
       g.psi = it.psi;
       g.lam = it.lam;
       g.partial = it.partial;
