@@ -511,8 +511,8 @@ def fused_extra(D, gates, state, scratch, ctx, n, steps, **kw):
     prof = D.profile_stop(ctx)
     pg = prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9 if prof["spmv_ms"] else None
     if kw.get("kron"):
-        kern = ("kron_big_kernel / kron_lds_kernel (Alg. 3, dense groups of up to %d qubits)" % kmax
-                if kmax > 3 else "kron_apply_kernel / kron_lds_kernel / kron_diag_kernel (Alg. 3)")
+        kern = ("kron_split_kernel / kron_apply_kernel / kron_lds_kernel (Alg. 3, dense groups of up to %d qubits)"
+                % kmax if kmax > 3 else "kron_apply_kernel / kron_lds_kernel / kron_diag_kernel (Alg. 3)")
     else:
         kern = "spmv_kernel (DiaQ SpMV, Alg. 2)"
     return {"plan": ("kron" if kw.get("kron") else "dia") + ("+fuse%d" % kmax if kw.get("fuse") else ""),
