@@ -464,6 +464,11 @@ typedef struct diaq_tuning {
                               XCD runs nor partner alternation apply: 0 launch
                               order, 1 each XCD a contiguous eighth of the
                               tiles, 2 the two halves interleaved */
+  int32_t spmv_pack;       /* complex64 products whose offsets and diagonal
+                              starts are all even (no coupling on qubit 0),
+                              with 16-byte aligned vectors, run on pairs of
+                              amplitudes as 16-byte units: 0 default (on),
+                              -1 never */
 } diaq_tuning_t;
 
 diaq_status_t diaq_set_tuning(diaq_ctx_t ctx, const diaq_tuning_t* t);
@@ -491,6 +496,10 @@ typedef struct diaq_spmv_shape {
   int32_t tile_order;      /* otherwise: 0 launch order, 1 XCD-contiguous
                               eighths, 2 halves interleaved */
   int64_t blocks;          /* workgroups of the launch */
+  int32_t packed;          /* 1: complex64 amplitudes taken in pairs (16-byte
+                              units; rows_per_lane then counts units, and
+                              tile_log2 and group_qubits are in amplitudes) */
+  int32_t reserved;
 } diaq_spmv_shape_t;
 diaq_status_t diaq_spmv_shape(const diaq_gate_t* gate, int32_t nqubits, diaq_dtype_t dtype,
                               const diaq_tuning_t* t, diaq_spmv_shape_t* out);

@@ -277,6 +277,7 @@ static diaq_status_t check_tuning(const diaq_tuning_t* t) {
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_small_qubits must be in [-1, 14]");
   if (t->kron_order < 0 || t->kron_order > 3) return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_order must be 0..3");
   if (t->spmv_order < 0 || t->spmv_order > 2) return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_order must be 0, 1 or 2");
+  if (t->spmv_pack < -1 || t->spmv_pack > 0) return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_pack must be 0 or -1");
   return DIAQ_OK;
 }
 

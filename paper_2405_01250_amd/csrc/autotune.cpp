@@ -161,6 +161,7 @@ void keep_other_knobs(const diaq_tuning_t& cur, diaq_tuning_t* best) {
   best->kron_small_qubits = cur.kron_small_qubits;
   best->kron_order = cur.kron_order;
   best->spmv_order = cur.spmv_order;
+  best->spmv_pack = cur.spmv_pack;
 }
 
 }  // namespace

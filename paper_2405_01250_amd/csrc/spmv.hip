@@ -51,6 +51,18 @@ template <>
 struct Vec<float> {
   using V = float2;
 };
+// Two consecutive complex64 amplitudes as one 16-byte unit (re0, im0, re1,
+// im1): complex64 products whose offsets and diagonal starts are all even
+// run on N / 2 units with halved offsets, so every state and diagonal
+// access is 16 bytes per lane, as in complex128 (8-byte accesses stream
+// more slowly; n = 28, mean over target qubits: U3 5.89 -> 6.13 TB/s, CX
+// 5.90 -> 6.16, diagonal gates 5.97 -> 6.36).  Each amplitude's sum is
+// formed as in the unpacked product, so the two agree exactly.
+struct Pk {};
+template <>
+struct Vec<Pk> {
+  using V = float4;
+};
 
 struct RowMap {
   int64_t N;
@@ -144,7 +156,19 @@ __device__ __forceinline__ void diag_at(const DiagArgs& da, const DiagSrc& src, 
 
 template <typename V>
 __device__ __forceinline__ bool nonzero(const V& v) {
-  return v.x != 0 || v.y != 0;
+  if constexpr (std::is_same<V, float4>::value) return v.x != 0 || v.y != 0 || v.z != 0 || v.w != 0;
+  else return v.x != 0 || v.y != 0;
+}
+
+// A packed unit's x entries behind a structural zero value stay zero (as
+// the skipped load leaves them in the unpacked product), so a non-finite x
+// there does not reach y.
+template <typename V>
+__device__ __forceinline__ void drop_behind_zeros(V& xv, const V& v) {
+  if constexpr (std::is_same<V, float4>::value) {
+    if (v.x == 0 && v.y == 0) xv.x = xv.y = 0;
+    if (v.z == 0 && v.w == 0) xv.z = xv.w = 0;
+  }
 }
 
 template <typename R>
@@ -154,16 +178,49 @@ __device__ __forceinline__ void cfma(typename Vec<R>::V& acc, const typename Vec
   acc.x = fma(-a.y, b.y, acc.x);
   acc.y = fma(a.x, b.y, acc.y);
   acc.y = fma(a.y, b.x, acc.y);
+  if constexpr (std::is_same<R, Pk>::value) {
+    acc.z = fma(a.z, b.z, acc.z);
+    acc.z = fma(-a.w, b.w, acc.z);
+    acc.w = fma(a.z, b.w, acc.w);
+    acc.w = fma(a.w, b.z, acc.w);
+  }
 }
 
 template <typename V>
-using NativeOf = typename HIP_vector_base<decltype(V{}.x), 2>::Native_vec_;
+__device__ __forceinline__ V vzero() {
+  V v;
+  v.x = 0;
+  v.y = 0;
+  if constexpr (std::is_same<V, float4>::value) {
+    v.z = 0;
+    v.w = 0;
+  }
+  return v;
+}
+
+template <typename V>
+__device__ __forceinline__ void vconj(V& v) {
+  v.y = -v.y;
+  if constexpr (std::is_same<V, float4>::value) v.w = -v.w;
+}
+
+template <typename V>
+struct NativeT {
+  using T = typename HIP_vector_base<decltype(V{}.x), 2>::Native_vec_;
+};
+template <>
+struct NativeT<float4> {
+  typedef float T __attribute__((ext_vector_type(4)));
+};
+template <typename V>
+using NativeOf = typename NativeT<V>::T;
 
 template <bool NT, typename V>
 __device__ __forceinline__ V ld(const V* p) {
   if constexpr (NT) {
     const auto t = __builtin_nontemporal_load(reinterpret_cast<const NativeOf<V>*>(p));
-    return V{t[0], t[1]};
+    if constexpr (std::is_same<V, float4>::value) return V{t[0], t[1], t[2], t[3]};
+    else return V{t[0], t[1]};
   } else {
     return *p;
   }
@@ -172,7 +229,13 @@ __device__ __forceinline__ V ld(const V* p) {
 template <bool NT, typename V>
 __device__ __forceinline__ void st(V* p, const V& v) {
   if constexpr (NT) {
-    NativeOf<V> t = {v.x, v.y};
+    NativeOf<V> t;
+    t[0] = v.x;
+    t[1] = v.y;
+    if constexpr (std::is_same<V, float4>::value) {
+      t[2] = v.z;
+      t[3] = v.w;
+    }
     __builtin_nontemporal_store(t, reinterpret_cast<NativeOf<V>*>(p));
   } else {
     *p = v;
@@ -199,7 +262,7 @@ __device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src,
 #pragma unroll
     for (int j = 0; j < RPT; j++) {
       row[s * RPT + j] = base + group_offset(s, m) + j * kBlock + threadIdx.x;
-      acc[s * RPT + j] = V{0, 0};
+      acc[s * RPT + j] = vzero<V>();
     }
   for (int k0 = 0; k0 < src.nd; k0 += KC) {
     // the chunk's diagonal descriptors first, so no value load waits on them
@@ -221,14 +284,14 @@ __device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src,
       for (int r = 0; r < ROWS; r++) {
         const int64_t i = row[r];
         in[c][r] = (i >= lok[c]) && (i < hik[c]) && (!CHECK || i < N);
-        v[c][r] = in[c][r] ? ld<NT>(vals + vbk[c] + i) : V{0, 0};
+        v[c][r] = in[c][r] ? ld<NT>(vals + vbk[c] + i) : vzero<V>();
       }
     }
     if (src.conjugate) {
 #pragma unroll
       for (int c = 0; c < KC; c++)
 #pragma unroll
-        for (int r = 0; r < ROWS; r++) v[c][r].y = -v[c][r].y;
+        for (int r = 0; r < ROWS; r++) vconj(v[c][r]);
     }
     // issue every x load of the chunk before the first multiply
     V xv[KC][ROWS];
@@ -236,8 +299,9 @@ __device__ __forceinline__ void dia_rows(const DiagArgs& da, const DiagSrc& src,
     for (int c = 0; c < KC; c++)
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        xv[c][r] = V{0, 0};
+        xv[c][r] = vzero<V>();
         if (in[c][r] && (!src.skip_zero || nonzero(v[c][r]))) xv[c][r] = x[row[r] + ek[c]];
+        if (src.skip_zero) drop_behind_zeros(xv[c][r], v[c][r]);
       }
     // ascending diagonal order within every row
 #pragma unroll
@@ -271,9 +335,9 @@ __global__ __launch_bounds__(kBlock) void diag_inplace_kernel(int64_t N, int32_t
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
     V v = ld<NT>(vals + i);
-    if (conjugate) v.y = -v.y;
+    if (conjugate) vconj(v);
     const V a = ld<NT>(xy + i);
-    V r{0, 0};
+    V r = vzero<V>();
     cfma<R>(r, v, a);
     st<NT>(xy + i, r);
   }
@@ -444,6 +508,10 @@ Plan plan_rows(const SpmvOp& op, const diaq_tuning_t& t, int rpt_override) {
   p.map.N = int64_t(1) << n;
   int rpt = rpt_override > 0 ? rpt_override : (t.spmv_rows > 0 ? t.spmv_rows : kDefaultRows);
   if (rpt != 1 && rpt != 2 && rpt != 4) rpt = kDefaultRows;
+  // with packing on, the rows knob counts 16-byte units (two complex64
+  // amplitudes): a complex64 product that cannot be packed takes twice as
+  // many rows per lane, the same bytes
+  if (op.dtype == DIAQ_C64 && t.spmv_pack >= 0 && rpt_override <= 0) rpt = std::min(4, 2 * rpt);
   int max_bits = t.spmv_group_bits < 0 ? 0 : (t.spmv_group_bits == 0 ? 3 : std::min(3, t.spmv_group_bits));
   if (op.nd > kMaxArgDiags) {
     // descriptor-table kernels come in one shape: 2 rows per lane, no grouping
@@ -533,11 +601,14 @@ void launch_one(diaq_ctx* ctx, const DiagArgs& da, const DiagSrc& src, const Pla
                 const typename Vec<R>::V* v, const typename Vec<R>::V* x, typename Vec<R>::V* y,
                 double2* partial, const typename Vec<R>::V* psi) {
   dim3 grid(unsigned(p.blocks)), block(kBlock);
-  if (partial)
-    hipLaunchKernelGGL((expect_kernel<R, RPT, G, CHK, KC, false, DM>), grid, block, 0, ctx->stream, da, src, p.map, v,
-                       psi, x, partial);
-  else
-    hipLaunchKernelGGL((spmv_kernel<R, RPT, G, CHK, KC, NT, DM>), grid, block, 0, ctx->stream, da, src, p.map, v, x, y);
+  if constexpr (!std::is_same<R, Pk>::value) {
+    if (partial) {
+      hipLaunchKernelGGL((expect_kernel<R, RPT, G, CHK, KC, false, DM>), grid, block, 0, ctx->stream, da, src, p.map,
+                         v, psi, x, partial);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((spmv_kernel<R, RPT, G, CHK, KC, NT, DM>), grid, block, 0, ctx->stream, da, src, p.map, v, x, y);
 }
 
 template <typename R, int RPT, int G, bool CHK>
@@ -602,6 +673,41 @@ diaq_status_t prepare(const SpmvOp& op, DiagArgs& da, DiagSrc& src) {
   return DIAQ_OK;
 }
 
+// complex64 products that run packed (two amplitudes per 16-byte unit):
+// every offset and diagonal start even, descriptors in the kernel
+// arguments, 16-byte aligned vectors, and the knob not off.
+bool packable(const SpmvOp& op, const diaq_tuning_t& t, const void* x, const void* y) {
+  if (op.dtype != DIAQ_C64 || t.spmv_pack < 0 || op.n < 2 || op.nd > kMaxArgDiags) return false;
+  for (int k = 0; k < op.nd; k++)
+    if ((op.host_off[k] & 1) || (op.host_start[k] & 1)) return false;
+  auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  return aligned(x) && aligned(y) && aligned(op.values);
+}
+
+// The packed problem: 2^(n-1) units, offsets and starts halved, coupling
+// qubits one lower (qubit q of the state is bit q - 1 of a unit index), and
+// the tile-pairing knobs moved down with them.
+struct PackedOp {
+  SpmvOp op;
+  int64_t off[kMaxArgDiags], start[kMaxArgDiags];
+  diaq_tuning_t t;
+};
+void pack_op(const SpmvOp& op, const diaq_tuning_t& t, PackedOp* P) {
+  P->op = op;
+  P->op.n = op.n - 1;
+  P->op.dtype = DIAQ_C128;  // planned as 16-byte elements
+  for (int k = 0; k < op.nd; k++) {
+    P->off[k] = op.host_off[k] / 2;
+    P->start[k] = op.host_start[k] / 2;
+  }
+  P->op.host_off = P->off;
+  P->op.host_start = P->start;
+  P->op.qubit_mask = op.qubit_mask >> 1;
+  P->t = t;
+  P->t.spmv_group_qubits = t.spmv_group_qubits >> 1;
+  P->t.spmv_group_min_qubit = (t.spmv_group_min_qubit > 0 ? t.spmv_group_min_qubit : kDefaultGroupMinQubit) - 1;
+}
+
 }  // namespace
 
 diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* y) {
@@ -616,11 +722,17 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
       return fail(DIAQ_ERR_INVALID_ARGUMENT, "x and y alias for a matrix with off-principal diagonals");
     const int64_t blocks = (N + kBlock - 1) / kBlock;  // one element per lane
     // complex128 streams with non-temporal hints (measured 5.76 -> 6.32
-    // TB/s at n = 28); complex64 is faster with plain accesses (5.95 against
-    // 5.03 TB/s)
+    // TB/s at n = 28), and so do complex64 pairs as 16-byte units (5.96 ->
+    // 6.36 TB/s against one amplitude per lane; 5.72 without the hints);
+    // single complex64 amplitudes are faster with plain accesses (5.95
+    // against 5.03 TB/s)
     if (op.dtype == DIAQ_C128)
       hipLaunchKernelGGL((diag_inplace_kernel<double, true>), dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream,
                          N, op.conjugate ? 1 : 0, static_cast<const double2*>(op.values), static_cast<double2*>(y));
+    else if (packable(op, ctx->tuning, y, y))
+      hipLaunchKernelGGL((diag_inplace_kernel<Pk, true>), dim3(unsigned((N / 2 + kBlock - 1) / kBlock)), dim3(kBlock),
+                         0, ctx->stream, N / 2, op.conjugate ? 1 : 0, static_cast<const float4*>(op.values),
+                         static_cast<float4*>(y));
     else
       hipLaunchKernelGGL((diag_inplace_kernel<float, false>), dim3(unsigned(blocks)), dim3(kBlock), 0, ctx->stream,
                          N, op.conjugate ? 1 : 0, static_cast<const float2*>(op.values), static_cast<float2*>(y));
@@ -629,6 +741,13 @@ diaq_status_t launch_spmv(diaq_ctx* ctx, const SpmvOp& op, const void* x, void* 
   }
   DiagArgs da;
   DiagSrc src;
+  if (packable(op, ctx->tuning, x, y)) {
+    PackedOp P;
+    pack_op(op, ctx->tuning, &P);
+    DIAQ_TRY(prepare(P.op, da, src));
+    const Plan p = plan_rows(P.op, P.t, ctx->spmv_rows);
+    return launch_typed<Pk>(ctx, P.op, da, src, p, op.values, x, y, nullptr, nullptr);
+  }
   DIAQ_TRY(prepare(op, da, src));
   const Plan p = plan_rows(op, ctx->tuning, ctx->spmv_rows);
   if (op.dtype == DIAQ_C128) return launch_typed<double>(ctx, op, da, src, p, op.values, x, y, nullptr, nullptr);
@@ -639,17 +758,23 @@ diaq_status_t spmv_shape(const SpmvOp& op, const diaq_tuning_t& t, diaq_spmv_sha
   std::memset(out, 0, sizeof(*out));
   for (int b = 0; b < 3; b++) out->group_qubits[b] = -1;
   const int64_t N = int64_t(1) << op.n;
+  // (aligned vectors assumed: the library's own allocations are)
+  static const char aligned_probe[16] __attribute__((aligned(16))) = {};
+  const bool packed = packable(op, t, aligned_probe, aligned_probe);
+  out->packed = packed ? 1 : 0;
   if (op.nd == 1 && op.host_off[0] == 0) {
     out->in_place = 1;
     out->rows_per_lane = 1;
     out->group = 1;
     out->chunk = 1;
-    out->nontemporal = op.dtype == DIAQ_C128 ? 1 : 0;
-    out->tile_log2 = 8;
-    out->blocks = (N + kBlock - 1) / kBlock;
+    out->nontemporal = (op.dtype == DIAQ_C128 || packed) ? 1 : 0;
+    out->tile_log2 = packed ? 9 : 8;
+    out->blocks = ((packed ? N / 2 : N) + kBlock - 1) / kBlock;
     return DIAQ_OK;
   }
-  const Plan p = plan_rows(op, t, 0);
+  PackedOp P;
+  if (packed) pack_op(op, t, &P);
+  const Plan p = packed ? plan_rows(P.op, P.t, 0) : plan_rows(op, t, 0);
   // the variant launch_typed instantiates for this plan
   out->rows_per_lane = p.rpt;
   out->group = p.g;
@@ -663,8 +788,10 @@ diaq_status_t spmv_shape(const SpmvOp& op, const diaq_tuning_t& t, diaq_spmv_sha
     out->chunk = p.kc;
     out->nontemporal = p.nt ? 1 : 0;
   }
-  out->tile_log2 = p.map.tile_log2;
-  for (int b = 0; b < p.map.ng; b++) out->group_qubits[b] = p.map.gbit[b];
+  // packed units: a tile of 2^t units holds 2^(t+1) amplitudes, unit bit b
+  // is qubit b + 1
+  out->tile_log2 = p.map.tile_log2 + (packed ? 1 : 0);
+  for (int b = 0; b < p.map.ng; b++) out->group_qubits[b] = p.map.gbit[b] + (packed ? 1 : 0);
   out->xcd_run_log2 = p.map.run_log2;
   out->pair_bit = p.map.pair_bit;
   out->tile_order = p.map.order;

@@ -59,14 +59,16 @@ class diaq_tuning_t(ctypes.Structure):
                 ("spmv_xcd_runs", ctypes.c_int32), ("spmv_group_qubits", ctypes.c_uint64),
                 ("kron_stage_qubit", ctypes.c_int32), ("kron_split", ctypes.c_int32),
                 ("kron_nontemporal", ctypes.c_int32), ("kron_small_qubits", ctypes.c_int32),
-                ("kron_order", ctypes.c_int32), ("spmv_order", ctypes.c_int32)]
+                ("kron_order", ctypes.c_int32), ("spmv_order", ctypes.c_int32),
+                ("spmv_pack", ctypes.c_int32)]
 
 
 class diaq_spmv_shape_t(ctypes.Structure):
     _fields_ = [("in_place", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("tile_log2", ctypes.c_int32),
                 ("group_qubits", ctypes.c_int32 * 3), ("xcd_run_log2", ctypes.c_int32),
-                ("pair_bit", ctypes.c_int32), ("tile_order", ctypes.c_int32), ("blocks", ctypes.c_int64)]
+                ("pair_bit", ctypes.c_int32), ("tile_order", ctypes.c_int32), ("blocks", ctypes.c_int64),
+                ("packed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class diaq_chain_step_t(ctypes.Structure):

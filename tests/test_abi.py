@@ -9,6 +9,7 @@ import subprocess
 
 import numpy as np
 import pytest
+import torch
 
 from paper_2405_01250_amd import diaq as D
 from paper_2405_01250_amd import inputs as W
@@ -116,7 +117,7 @@ def test_struct_layouts_match_header(tmp_path):
     field offsets (a C program built from include/diaq.h prints them)."""
     structs = {"diaq_gate_t": D.diaq_gate_t, "diaq_plan_t": D.diaq_plan_t, "diaq_tuning_t": D.diaq_tuning_t,
                "diaq_profile_t": D.diaq_profile_t, "diaq_circuit_t": D.diaq_circuit_t,
-               "diaq_chain_step_t": D.diaq_chain_step_t}
+               "diaq_chain_step_t": D.diaq_chain_step_t, "diaq_spmv_shape_t": D.diaq_spmv_shape_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "diaq.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
@@ -270,6 +271,32 @@ def test_spmv_shape_host_only(lib):
         D.spmv_shape(W.u3(0.1, 0.2, 0.3, 28), 28)
     with pytest.raises(D.DiaqError):
         D.spmv_shape(W.u3(0.1, 0.2, 0.3, 3), 28, spmv_rows=3)
+
+
+def test_spmv_shape_packed_complex64(lib):
+    """Complex64 products with even offsets run on pairs of amplitudes: the
+    units of a launch cover the state once, tiles and paired coupling qubits
+    are reported in amplitudes; a coupling on qubit 0, complex128, or the
+    knob at -1 keep one amplitude per access."""
+    c64 = torch.complex64
+    n = 28
+    for q in (1, 5, 9, 14, 27):
+        s = D.spmv_shape(W.u3(0.1, 0.2, 0.3, q), n, c64)
+        assert s["packed"] == 1, q
+        units = s["rows_per_lane"] * s["group"] * 256
+        assert s["blocks"] * units * 2 == 1 << n, (q, s)
+        assert s["tile_log2"] == 9 + s["rows_per_lane"].bit_length() - 1, (q, s)
+        assert all(g >= s["tile_log2"] for g in s["group_qubits"]), (q, s)
+    assert D.spmv_shape(W.u3(0.1, 0.2, 0.3, 27), n, c64)["group_qubits"] == [27]
+    assert D.spmv_shape(W.u3(0.1, 0.2, 0.3, 0), n, c64)["packed"] == 0
+    assert D.spmv_shape(W.cx(5, 0), n, c64)["packed"] == 0
+    assert D.spmv_shape(W.cx(0, 5), n, c64)["packed"] == 1
+    assert D.spmv_shape(W.u3(0.1, 0.2, 0.3, 5), n, c64, spmv_pack=-1)["packed"] == 0
+    assert D.spmv_shape(W.u3(0.1, 0.2, 0.3, 5), n)["packed"] == 0
+    s = D.spmv_shape(W.Gate("RZ", (5,), (), (0.3,)), n, c64)
+    assert (s["in_place"], s["packed"], s["blocks"]) == (1, 1, (1 << (n - 1)) // 256)
+    with pytest.raises(D.DiaqError):
+        D.spmv_shape(W.u3(0.1, 0.2, 0.3, 5), n, c64, spmv_pack=1)
 
 
 def test_small_circuit_kernel_reads_gates_from_the_argument_segment():

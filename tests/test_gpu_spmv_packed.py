@@ -1,0 +1,130 @@
+"""Complex64 products on pairs of amplitudes (16-byte units, tuning knob
+spmv_pack): products whose offsets and diagonal starts are all even run on
+N / 2 units with halved offsets.  Against the unpacked product (knob -1),
+which sums every row in the same order, so the two agree exactly, and
+against the oracle at the complex64 bar; the structural-zero and
+non-finite semantics of both matrix kinds; the in-place diagonal kernel."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2405_01250_amd import diaq as D
+from paper_2405_01250_amd import inputs as W
+from tests.gpu_util import assert_state_close, to_dev, to_host
+from tests.test_gpu_kernels import _classes
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+C64 = torch.complex64
+
+
+@pytest.fixture()
+def ctx():
+    c = D.context()
+    saved = D.get_tuning(c)
+    yield c
+    D.set_tuning(c, **saved)
+
+
+def _gates(n, rng):
+    gs = []
+    for q in range(n):
+        gs.append(W.u3(*rng.uniform(0, 6, 3), q))
+    gs += [W.cx(0, n - 1), W.cx(n - 1, 0), W.cx(3, 7), W.Gate("X", (5,), (0, 2)), W.swap(1, n - 2), W.swap(2, 9),
+           W.Gate("RXX", (4, n - 1), (), (0.4,)), W.Gate("RZ", (0,), (), (0.7,)), W.cz(0, 6),
+           W.Gate("RZZ", (3, 8), (), (1.3,))]
+    return gs
+
+
+@pytest.mark.parametrize("n", [12, 20])
+def test_packed_equals_unpacked_and_oracle(ctx, n):
+    rng = np.random.default_rng(n)
+    gates = _gates(n, rng)
+    x = W.random_state(n, n)
+    ref = orc.apply_circuit(x, n, gates)
+    out = {}
+    for pack in (0, -1):
+        D.set_tuning(ctx, spmv_pack=pack)
+        for name, plan in (("plain", None), ("fuse2", D.make_plan(fuse=True, max_fused_qubits=2)),
+                           ("fuse3", D.make_plan(fuse=True, max_fused_qubits=3))):
+            psi = to_dev(x, C64)
+            D.apply_circuit(gates, psi, plan=plan)
+            out[(pack, name)] = to_host(psi)
+            assert_state_close(out[(pack, name)], ref, TOL32, "%s pack %d" % (name, pack), l2tol=1e-4)
+    for name in ("plain", "fuse2", "fuse3"):
+        assert np.array_equal(out[(0, name)], out[(-1, name)]), name
+    # single products, also adjoint
+    for g in gates:
+        A = D.from_gate(g, n, dtype=C64)
+        xs = to_dev(x, C64)
+        ys = {}
+        for pack in (0, -1):
+            D.set_tuning(ctx, spmv_pack=pack)
+            ys[pack] = (to_host(D.spmv(A, xs)), to_host(D.spmv(A, xs, flags=D.ADJOINT)))
+        assert np.array_equal(ys[0][0], ys[-1][0]) and np.array_equal(ys[0][1], ys[-1][1]), g
+
+
+def test_packed_structural_zeros_skip_non_finite_x(ctx):
+    """Controls on qubit 0 make the two amplitudes of a unit differ: one row
+    of the pair couples, the other holds a structural zero.  A non-finite x
+    reaches exactly the rows whose matrix column is non-zero, as unpacked."""
+    D.set_tuning(ctx, spmv_pack=0)
+    n = 10
+    x = W.random_state(n, 9)
+    col = 300
+    x[col] = np.inf
+    xf = x.copy()
+    xf[col] = 0
+    for g in [W.cx(0, 2), W.cx(0, 8), W.Gate("X", (4,), (0, 1)), W.u3(0.3, 1.1, 2.2, 3), W.swap(1, 8)]:
+        Ad = orc.dense_matrix(n, [g])
+        assert D.spmv_shape(g, n, C64)["packed"] == 1, g
+        got = to_host(D.spmv(D.from_gate(g, n, dtype=C64), to_dev(x, C64)))
+        hit = Ad[:, col] != 0
+        assert not np.isfinite(got[hit]).any(), g
+        assert np.max(np.abs(got[~hit] - (Ad @ xf)[~hit])) <= TOL32, g
+
+
+@pytest.mark.parametrize("bad", [np.inf, np.nan])
+def test_packed_caller_matrix_propagates_non_finite_x(ctx, bad):
+    """A caller-built complex64 matrix with even offsets (packed): explicit
+    zeros multiply their x entries (0 * Inf = NaN), as in Alg. 2."""
+    D.set_tuning(ctx, spmv_pack=0)
+    rng = np.random.default_rng(33)
+    n = 10
+    N = 1 << n
+    diags = {}
+    for d in (-300, -4, 0, 6, 258):
+        L = N - abs(d)
+        diags[d] = (rng.standard_normal(L) + 1j * rng.standard_normal(L)).astype(np.complex64)
+    diags[6][:] = 0
+    diags[-4][::7] = 0
+    A = D.from_dense_diagonals(n, diags, dtype=C64)
+    x = W.random_state(n, 8).astype(np.complex64)
+    for c in (0, 37, 518, N - 1):
+        x[c] = bad
+    o, s_, v = orc.pack_dia(sorted(diags), [diags[d].astype(np.complex128) for d in sorted(diags)])
+    ref = orc.dia_spmv(N, o, s_, v, x.astype(np.complex128))
+    got = to_host(D.spmv(A, to_dev(x, C64)))
+    assert (_classes(got) == _classes(ref)).all()
+    fin = np.isfinite(ref)
+    assert np.max(np.abs(got[fin] - ref[fin])) <= 1e-4
+
+
+def test_packed_in_place_diagonal(ctx):
+    n = 16
+    x = W.random_state(n, 5)
+    g = W.Gate("RZZ", (2, 11), (), (0.9,))
+    ref = x.copy()
+    orc.apply_gate(ref, n, g)
+    outs = []
+    for pack in (0, -1):
+        D.set_tuning(ctx, spmv_pack=pack)
+        psi = to_dev(x, C64)
+        D.apply_circuit([g], psi)
+        outs.append(to_host(psi))
+        assert_state_close(outs[-1], ref, TOL32, "pack %d" % pack)
+    assert np.array_equal(outs[0], outs[1])
