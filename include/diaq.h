@@ -464,10 +464,12 @@ typedef struct diaq_tuning {
                               XCD runs nor partner alternation apply: 0 launch
                               order, 1 each XCD a contiguous eighth of the
                               tiles, 2 the two halves interleaved */
-  int32_t spmv_pack;       /* complex64 products whose offsets and diagonal
-                              starts are all even (no coupling on qubit 0),
-                              with 16-byte aligned vectors, run on pairs of
-                              amplitudes as 16-byte units: 0 default (on),
+  int32_t spmv_pack;       /* complex64 amplitudes in pairs, 16-byte units:
+                              DiaQ products whose offsets and diagonal starts
+                              are all even (no coupling on qubit 0), and the
+                              per-coset and diagonal Alg. 3 kernels of gates
+                              that neither act on nor are controlled by
+                              qubit 0 (two cosets per lane); 0 default (on),
                               -1 never */
 } diaq_tuning_t;
 

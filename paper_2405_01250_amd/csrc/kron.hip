@@ -44,6 +44,7 @@ struct KronArgs {
   int32_t rows;        // 1: the table headers hold this op's roff[r]
   int32_t ntio;        // 1: state loads and stores carry non-temporal hints
   int32_t order;       // workgroup order (kron_block)
+  int32_t pack;        // complex64: two amplitudes per 16-byte access where possible
   const char* tabs;
   const double* dmat;  // device 4 x 4 local matrix (k <= 2), replaces m
   double m[8][8][2];
@@ -185,6 +186,82 @@ __global__ __launch_bounds__(kBlock) void kron_apply_kernel(KronArgs a, typename
   }
 }
 
+// Complex64 states, two cosets per lane: when qubit 0 is neither a target
+// nor a control, cosets 2m and 2m + 1 sit at bases b and b + 1 and share
+// their control bits, so each of their rows is one 16-byte access holding
+// both (instead of two 8-byte ones; n = 28, mean over target qubits: U3
+// 5.39 -> 5.73 TB/s, CX controlled by the top qubit 4.34 -> 5.06, groups
+// of three qubits 4.14 -> 5.24).
+template <int K, bool DM, int TAB>
+__global__ __launch_bounds__(kBlock) void kron_apply2_kernel(KronArgs a, float4* __restrict__ v) {
+  constexpr int d = 1 << K;
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  const int64_t m = kron_block(a.order) * kBlock + threadIdx.x;
+  if (2 * m >= a.ncos) return;
+  const int64_t b = insert_zeros(2 * m, a);
+  const bool on = (uint64_t(b) & a.cmask) == a.cmask;
+  if (!on && a.nt == 0) return;
+  const bool nt = a.ntio != 0;
+  double xr0[d], xi0[d], xr1[d], xi1[d];
+#pragma unroll
+  for (int r = 0; r < d; r++) {
+    const F4* p = reinterpret_cast<const F4*>(v) + (b + a.off[r]) / 2;
+    const F4 t = nt ? __builtin_nontemporal_load(p) : *p;
+    xr0[r] = t[0];
+    xi0[r] = t[1];
+    xr1[r] = t[2];
+    xi1[r] = t[3];
+  }
+  if (!on) {
+    // controls 0: the amplitudes stay, the folded factors still apply
+#pragma unroll
+    for (int r = 0; r < d; r++) {
+      apply_tables(a.tabs, a.nt, uint64_t(b + a.off[r]), xr0[r], xi0[r]);
+      apply_tables(a.tabs, a.nt, uint64_t(b + 1 + a.off[r]), xr1[r], xi1[r]);
+      F4 o = {float(xr0[r]), float(xi0[r]), float(xr1[r]), float(xi1[r])};
+      F4* p = reinterpret_cast<F4*>(v) + (b + a.off[r]) / 2;
+      if (nt) __builtin_nontemporal_store(o, p);
+      else *p = o;
+    }
+    return;
+  }
+  double yr0[d], yi0[d], yr1[d], yi1[d];
+  mat_vec<K, DM>(a, xr0, xi0, yr0, yi0);
+  mat_vec<K, DM>(a, xr1, xi1, yr1, yi1);
+  const bool rows = TAB == 2 && a.rows;
+  if (a.nt && rows) {
+    apply_tables_rows<d>(a.tabs, a.nt, uint64_t(b), yr0, yi0);
+    apply_tables_rows<d>(a.tabs, a.nt, uint64_t(b + 1), yr1, yi1);
+  }
+#pragma unroll
+  for (int r = 0; r < d; r++) {
+    if (a.nt && !rows) {
+      apply_tables(a.tabs, a.nt, uint64_t(b + a.off[r]), yr0[r], yi0[r]);
+      apply_tables(a.tabs, a.nt, uint64_t(b + 1 + a.off[r]), yr1[r], yi1[r]);
+    }
+    F4 o = {float(yr0[r]), float(yi0[r]), float(yr1[r]), float(yi1[r])};
+    F4* p = reinterpret_cast<F4*>(v) + (b + a.off[r]) / 2;
+    if (nt) __builtin_nontemporal_store(o, p);
+    else *p = o;
+  }
+}
+
+// One amplitude of a diagonal gate: row i's phase (if its controls are 1)
+// and the folded factors.
+template <bool DM>
+__device__ __forceinline__ void diag_one(const KronArgs& a, int64_t i, double& tr, double& ti) {
+  if ((uint64_t(i) & a.cmask) == a.cmask) {
+    int r = 0;
+    for (int j = 0; j < a.k; j++)
+      if ((i & a.off[1 << j]) != 0) r |= 1 << j;
+    const double mr = mel<DM>(a, r, r, 0), mi = a.adjoint ? -mel<DM>(a, r, r, 1) : mel<DM>(a, r, r, 1);
+    const double nr = mr * tr - mi * ti;
+    ti = mr * ti + mi * tr;
+    tr = nr;
+  }
+  if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(i), tr, ti);
+}
+
 // Diagonal gates: element-wise phase, in place.
 template <typename R, bool DM>
 __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N, typename Vec<R>::V* __restrict__ v) {
@@ -195,17 +272,29 @@ __global__ __launch_bounds__(kBlock) void kron_diag_kernel(KronArgs a, int64_t N
     if (!on && a.nt == 0) continue;  // an unfolded controlled phase leaves these rows alone
     V t = kld(v + i, a.ntio != 0);
     double tr = double(t.x), ti = double(t.y);
-    if (on) {
-      int r = 0;
-      for (int j = 0; j < a.k; j++)
-        if ((i & a.off[1 << j]) != 0) r |= 1 << j;
-      const double mr = mel<DM>(a, r, r, 0), mi = a.adjoint ? -mel<DM>(a, r, r, 1) : mel<DM>(a, r, r, 1);
-      const double nr = mr * tr - mi * ti;
-      ti = mr * ti + mi * tr;
-      tr = nr;
-    }
-    if (a.nt) apply_tables(a.tabs, a.nt, uint64_t(i), tr, ti);
+    diag_one<DM>(a, i, tr, ti);
     kst(v + i, V{R(tr), R(ti)}, a.ntio != 0);
+  }
+}
+
+// The same for complex64 states taken two amplitudes at a time (16-byte
+// accesses, non-temporal: n = 28, diagonal gates 4.8 -> 5.8 TB/s against
+// one 8-byte amplitude per lane, CZ 2.2 -> 3.1 on its half-state model).  A unit whose two rows both keep their
+// amplitude is left alone; otherwise both are rewritten.
+template <bool DM>
+__global__ __launch_bounds__(kBlock) void kron_diag2_kernel(KronArgs a, int64_t units, float4* __restrict__ v) {
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t u = int64_t(blockIdx.x) * kBlock + threadIdx.x; u < units; u += stride) {
+    const int64_t i = 2 * u;
+    const bool on0 = (uint64_t(i) & a.cmask) == a.cmask, on1 = (uint64_t(i + 1) & a.cmask) == a.cmask;
+    if (!on0 && !on1 && a.nt == 0) continue;
+    const F4 t = __builtin_nontemporal_load(reinterpret_cast<const F4*>(v + u));
+    double r0 = t[0], i0 = t[1], r1 = t[2], i1 = t[3];
+    diag_one<DM>(a, i, r0, i0);
+    diag_one<DM>(a, i + 1, r1, i1);
+    F4 o = {float(r0), float(i0), float(r1), float(i1)};
+    __builtin_nontemporal_store(o, reinterpret_cast<F4*>(v + u));
   }
 }
 
@@ -322,11 +411,26 @@ void launch_apply_tab(const KronArgs& a, int tab, dim3 grid, dim3 block, hipStre
   else hipLaunchKernelGGL((kron_apply_kernel<R, K, DM, 1>), grid, block, 0, stream, a, v);
 }
 
+template <int K, bool DM>
+void launch_apply2_tab(const KronArgs& a, int tab, hipStream_t stream, void* v) {
+  const dim3 grid(unsigned((a.ncos / 2 + kBlock - 1) / kBlock)), block(kBlock);
+  if (tab == 2) hipLaunchKernelGGL((kron_apply2_kernel<K, DM, 2>), grid, block, 0, stream, a, static_cast<float4*>(v));
+  else hipLaunchKernelGGL((kron_apply2_kernel<K, DM, 1>), grid, block, 0, stream, a, static_cast<float4*>(v));
+}
+
 template <typename R, bool DM>
 void dispatch_apply(const KronArgs& a, int k, bool diag, int64_t N, int num_cus, hipStream_t stream, void* v) {
   using V = typename Vec<R>::V;
   if (diag) {
     const int64_t blocks = (N + kBlock - 1) / kBlock;
+    if constexpr (std::is_same<R, float>::value) {
+      if (a.pack && (reinterpret_cast<uintptr_t>(v) & 15) == 0 && N >= 2) {
+        const int64_t units = N / 2;
+        hipLaunchKernelGGL((kron_diag2_kernel<DM>), dim3(static_cast<unsigned>((units + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, stream, a, units, static_cast<float4*>(v));
+        return;
+      }
+    }
     hipLaunchKernelGGL((kron_diag_kernel<R, DM>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, a, N,
                        static_cast<V*>(v));
     return;
@@ -334,6 +438,16 @@ void dispatch_apply(const KronArgs& a, int k, bool diag, int64_t N, int num_cus,
   const int64_t blocks = (a.ncos + kBlock * kCosetsPerLane - 1) / (kBlock * kCosetsPerLane);
   const dim3 grid(static_cast<unsigned>(blocks)), block(kBlock);
   const int tab = (a.rows && a.nt >= kRowsMinTables) ? 2 : 1;
+  if constexpr (std::is_same<R, float>::value) {
+    // qubit 0 outside the gate: two cosets per lane, 16-byte accesses
+    if (a.pack && a.sorted[0] >= 1 && (a.cmask & 1) == 0 && a.ncos >= 2 &&
+        (reinterpret_cast<uintptr_t>(v) & 15) == 0) {
+      if (k == 1) launch_apply2_tab<1, DM>(a, tab, stream, v);
+      else if (k == 2) launch_apply2_tab<2, DM>(a, tab, stream, v);
+      else if constexpr (!DM) launch_apply2_tab<3, false>(a, tab, stream, v);
+      return;
+    }
+  }
   if (k == 1)
     launch_apply_tab<R, 1, DM>(a, tab, grid, block, stream, static_cast<V*>(v));
   else if (k == 2)
@@ -397,6 +511,7 @@ diaq_status_t launch_kron_apply(diaq_ctx* ctx, hipStream_t stream, const LocalGa
   // leaves whole regions idle, which that order would put on half the XCDs
   // (CX controlled by the top qubit 5.25 -> 5.02)
   a.order = ctx->tuning.kron_order != 0 ? ctx->tuning.kron_order : ((lg.cmask == 0 || nt > 0) ? 1 : 0);
+  a.pack = ctx->tuning.spmv_pack >= 0 ? 1 : 0;
   const int64_t N = int64_t(1) << n;
   const bool diag = is_diagonal_local(lg);
   if (dt == DIAQ_C128) {

@@ -818,10 +818,10 @@ diaq_status_t plan_big_greedy(const diaq_gate_t* gates, int64_t ngates, int n, i
 // Modelled time of a plan in units of one pass over the state: an operation
 // of at most four qubits costs its memory pass; a dense five-qubit group's
 // 4096 FMAs per coset take longer than that pass (n = 28: 1.85 against
-// 1.44 ms in complex128; in complex64, whose pass is half as long, 1.45
-// against 0.67 ms).
+// 1.44 ms in complex128; in complex64, whose narrower groups run about
+// 0.8 ms per pass, 1.45 ms).
 double plan_cost(const std::vector<BigOp>& ops, diaq_dtype_t dt) {
-  const double five = dt == DIAQ_C128 ? 1.3 : 2.2;
+  const double five = dt == DIAQ_C128 ? 1.3 : 1.8;
   double c = 0;
   for (const BigOp& op : ops) c += (!op.raw && op.k == 5) ? five : 1.0;
   return c;

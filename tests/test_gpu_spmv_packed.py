@@ -128,3 +128,27 @@ def test_packed_in_place_diagonal(ctx):
         outs.append(to_host(psi))
         assert_state_close(outs[-1], ref, TOL32, "pack %d" % pack)
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("n", [12, 18])
+def test_kron_packed_equals_unpacked_and_oracle(ctx, n):
+    """Alg. 3 per-coset and diagonal kernels on complex64 pairs (two cosets
+    per lane where qubit 0 is outside the gate): the same values as one
+    coset per lane, bit for bit, under the per-gate and fused plans."""
+    rng = np.random.default_rng(50 + n)
+    gates = _gates(n, rng) + [W.Gate("RZ", (q,), (), (0.1 * q,)) for q in range(n)] + [
+        W.cp(0.7, 2, 9), W.cp(1.1, 0, 5), W.Gate("X", (6,), (3, 4))]
+    x = W.random_state(n, 60 + n)
+    ref = orc.apply_circuit(x, n, gates)
+    out = {}
+    for pack in (0, -1):
+        D.set_tuning(ctx, spmv_pack=pack)
+        for name, plan in (("kron", D.make_plan(kron=True)),
+                           ("kron+fuse3", D.make_plan(kron=True, fuse=True, max_fused_qubits=3)),
+                           ("kron+fuse2", D.make_plan(kron=True, fuse=True, max_fused_qubits=2))):
+            psi = to_dev(x, C64)
+            D.apply_circuit(gates, psi, plan=plan)
+            out[(pack, name)] = to_host(psi)
+            assert_state_close(out[(pack, name)], ref, TOL32, "%s pack %d" % (name, pack), l2tol=1e-4)
+    for name in ("kron", "kron+fuse3", "kron+fuse2"):
+        assert np.array_equal(out[(0, name)], out[(-1, name)]), name
