@@ -527,7 +527,8 @@ def fused_extra(D, gates, state, scratch, ctx, n, steps, **kw):
 def c64_extra(D, W, torch, gates, steps):
     """The same circuit on the plain path in complex64 (8-byte amplitudes):
     gates/s and the kernels' rates, with the autotuned knobs for complex64
-    (the complex128 knobs are restored afterwards)."""
+    (the complex128 knobs are restored afterwards); also its time under the
+    Alg. 3 plan with groups of up to four qubits."""
     n = max(max(g.targets + tuple(g.controls)) for g in gates) + 1
     ctx = D.context()
     saved = D.get_tuning(ctx)
@@ -546,13 +547,23 @@ def c64_extra(D, W, torch, gates, steps):
     dt = time.perf_counter() - t0
     p = D.profile_stop(ctx)
     norm = float(torch.linalg.vector_norm(psi.to(torch.complex128)).item())
+    # the Alg. 3 plan with groups of up to four qubits, in complex64
+    plan = D.make_plan(kron=True, fuse=True, max_fused_qubits=4)
+    D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    dk = time.perf_counter() - t0
     D.set_tuning(ctx, **saved)
     del psi, scratch
     torch.cuda.empty_cache()
     return {"workload": "random layered n=%d, %d gates, complex64, plain path" % (n, len(gates)),
             "gates_per_s": round(len(gates) * steps / dt, 2), "ms_per_step": round(dt / steps * 1e3, 1),
             "spmv_GBps": round(p["spmv_bytes"] / p["spmv_ms"] / 1e6, 1),
-            "expand_GBps": round(p["expand_bytes"] / p["expand_ms"] / 1e6, 1), "final_norm": norm}
+            "expand_GBps": round(p["expand_bytes"] / p["expand_ms"] / 1e6, 1), "final_norm": norm,
+            "kron_fuse4_gates_per_s": round(len(gates) * steps / dk, 1), "kron_fuse4_ms": round(dk / steps * 1e3, 2)}
 
 
 def tfim_extra(D, W, torch, ctx, state, scratch, tdt):
