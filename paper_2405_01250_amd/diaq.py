@@ -549,14 +549,15 @@ def expect_noalloc(H: DiaqMatrix, psi: torch.Tensor, out: torch.Tensor, phi: tor
 
 
 def adjoint_grad(gates: Sequence, H: DiaqMatrix, psi0: torch.Tensor, nparams: int,
-                 work: torch.Tensor | None = None, plan: diaq_plan_t | None = None):
-    """(E, dE/dtheta) by the adjoint reverse sweep; synchronises."""
+                 work: torch.Tensor | None = None, plan: diaq_plan_t | None = None, marshalled=None):
+    """(E, dE/dtheta) by the adjoint reverse sweep; synchronises.  marshalled:
+    gate_array(gates) from an earlier call, reused as it is."""
     n, _, dt, _, _ = H.info()
     if work is None:
         work = torch.empty(3 << n, dtype=psi0.dtype, device=psi0.device)
     if work.numel() < (3 << n) or work.dtype != psi0.dtype or not work.is_contiguous():
         raise ValueError("work must hold 3 * 2^n contiguous elements of the state dtype")
-    arr, keep = gate_array(gates)
+    arr, keep = marshalled if marshalled is not None else gate_array(gates)
     e = _D()
     grad = np.zeros(max(nparams, 1), dtype=np.float64)
     _check(load().diaq_adjoint_grad(H.ctx.handle, arr, len(gates), n, dt, H.handle, _vec(psi0, n, dt, "psi0"),
