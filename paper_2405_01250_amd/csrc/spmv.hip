@@ -705,7 +705,9 @@ void pack_op(const SpmvOp& op, const diaq_tuning_t& t, PackedOp* P) {
   P->op.qubit_mask = op.qubit_mask >> 1;
   P->t = t;
   P->t.spmv_group_qubits = t.spmv_group_qubits >> 1;
-  P->t.spmv_group_min_qubit = (t.spmv_group_min_qubit > 0 ? t.spmv_group_min_qubit : kDefaultGroupMinQubit) - 1;
+  // (a threshold of qubit 1 stays 1: 0 would mean the default)
+  P->t.spmv_group_min_qubit =
+      std::max(1, (t.spmv_group_min_qubit > 0 ? t.spmv_group_min_qubit : kDefaultGroupMinQubit) - 1);
 }
 
 }  // namespace
