@@ -511,8 +511,9 @@ def fused_extra(D, gates, state, scratch, ctx, n, steps, **kw):
     prof = D.profile_stop(ctx)
     pg = prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9 if prof["spmv_ms"] else None
     if kw.get("kron"):
-        kern = ("kron_split_kernel / kron_apply_kernel / kron_lds_kernel (Alg. 3, dense groups of up to %d qubits)"
-                % kmax if kmax > 3 else "kron_apply_kernel / kron_lds_kernel / kron_diag_kernel (Alg. 3)")
+        kern = ("kron_split_kernel / kron_mfmap_kernel / kron_apply_kernel / kron_lds_kernel (Alg. 3, dense "
+                "groups of up to %d qubits)" % kmax if kmax > 3
+                else "kron_apply_kernel / kron_lds_kernel / kron_diag_kernel (Alg. 3)")
     else:
         kern = "spmv_kernel (DiaQ SpMV, Alg. 2)"
     return {"plan": ("kron" if kw.get("kron") else "dia") + ("+fuse%d" % kmax if kw.get("fuse") else ""),
@@ -528,7 +529,7 @@ def c64_extra(D, W, torch, gates, steps):
     """The same circuit on the plain path in complex64 (8-byte amplitudes):
     gates/s and the kernels' rates, with the autotuned knobs for complex64
     (the complex128 knobs are restored afterwards); also its time under the
-    Alg. 3 plan with groups of up to four qubits."""
+    Alg. 3 plans with groups of up to four and up to five qubits."""
     n = max(max(g.targets + tuple(g.controls)) for g in gates) + 1
     ctx = D.context()
     saved = D.get_tuning(ctx)
@@ -556,6 +557,16 @@ def c64_extra(D, W, torch, gates, steps):
         D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan, marshalled=arr, ctx=ctx)
     torch.cuda.synchronize()
     dk = time.perf_counter() - t0
+    # and with groups of up to five qubits (those whose qubits are all >= 4
+    # on the fp32 matrix cores)
+    plan5 = D.make_plan(kron=True, fuse=True, max_fused_qubits=5)
+    D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan5, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        D.apply_circuit(gates, psi, n=n, scratch=scratch, plan=plan5, marshalled=arr, ctx=ctx)
+    torch.cuda.synchronize()
+    d5 = time.perf_counter() - t0
     D.set_tuning(ctx, **saved)
     del psi, scratch
     torch.cuda.empty_cache()
@@ -563,7 +574,8 @@ def c64_extra(D, W, torch, gates, steps):
             "gates_per_s": round(len(gates) * steps / dt, 2), "ms_per_step": round(dt / steps * 1e3, 1),
             "spmv_GBps": round(p["spmv_bytes"] / p["spmv_ms"] / 1e6, 1),
             "expand_GBps": round(p["expand_bytes"] / p["expand_ms"] / 1e6, 1), "final_norm": norm,
-            "kron_fuse4_gates_per_s": round(len(gates) * steps / dk, 1), "kron_fuse4_ms": round(dk / steps * 1e3, 2)}
+            "kron_fuse4_gates_per_s": round(len(gates) * steps / dk, 1), "kron_fuse4_ms": round(dk / steps * 1e3, 2),
+            "kron_fuse5_gates_per_s": round(len(gates) * steps / d5, 1), "kron_fuse5_ms": round(d5 / steps * 1e3, 2)}
 
 
 def tfim_extra(D, W, torch, ctx, state, scratch, tdt):

@@ -443,7 +443,14 @@ typedef struct diaq_tuning {
                               from LDS for every tile, 5 the same with the
                               matrix held in registers, 6 rows split as in 2
                               with five-qubit products formed from three
-                              real multiplications per complex one */
+                              real multiplications per complex one, 7
+                              products of 16 cosets at a time on the matrix
+                              cores with each wave's next inputs loaded
+                              during its products, in the state's precision
+                              (complex64: fp32 operands and sums; groups
+                              whose qubits are all >= 4, others take the
+                              default).  The default uses 7 for such groups
+                              of five qubits, and of four in complex64. */
   int32_t kron_nontemporal;/* per-coset Alg. 3 kernel state streams: 0 default,
                               1 non-temporal hints, -1 plain accesses */
   int32_t kron_small_qubits; /* plan.kron on at most this many qubits runs

@@ -270,7 +270,7 @@ static diaq_status_t check_tuning(const diaq_tuning_t* t) {
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "spmv_xcd_runs must be 0 or -1");
   if (t->kron_stage_qubit < -1 || t->kron_stage_qubit > 6)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_stage_qubit must be in [-1, 6]");
-  if (t->kron_split < 0 || t->kron_split > 6) return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_split must be in [0, 6]");
+  if (t->kron_split < 0 || t->kron_split > 7) return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_split must be in [0, 7]");
   if (t->kron_nontemporal < -1 || t->kron_nontemporal > 1)
     return fail(DIAQ_ERR_INVALID_ARGUMENT, "kron_nontemporal must be -1, 0 or 1");
   if (t->kron_small_qubits < -1 || t->kron_small_qubits > 14)

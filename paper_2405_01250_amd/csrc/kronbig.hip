@@ -516,7 +516,7 @@ struct MfmaArgs {
   int32_t sorted[5];   // group qubits ascending
   int32_t pad;
   int64_t off[32];     // element offset of local index r
-  const double* lmat;  // real matrix in operand order, [(i S + s) 64 + lane]
+  const double* lmat;  // real matrix in operand order, [(i S + s) 64 + lane] (fp32 values for kron_mfmap_kernel<float>)
   const char* tabs;
 };
 
@@ -611,6 +611,177 @@ void launch_mfma(const MfmaArgs& a, int k, bool hold, int num_cus, hipStream_t s
   if (k == 4) hipLaunchKernelGGL((kron_mfma_kernel<R, 4, true>), grid, block, 0, stream, a, v);
   else if (hold) hipLaunchKernelGGL((kron_mfma_kernel<R, 5, true>), grid, block, 0, stream, a, v);
   else hipLaunchKernelGGL((kron_mfma_kernel<R, 5, false>), grid, block, 0, stream, a, v);
+}
+
+// Pipelined matrix-core groups: the same real (2D x 2D) * (2D x 16)
+// product per 16 cosets as kron_mfma_kernel, arranged so that the memory
+// stream and the matrix cores overlap.  Each wave loads the inputs of its
+// next tile into a second register buffer before it multiplies the current
+// one; the matrix stays in LDS (a.lmat holds the operand-order table in the
+// state's precision), re-read for every tile, which leaves registers for
+// four or more waves per SIMD; lane l's element offsets split into a
+// wave-uniform part and a part fixed by l / 16, formed once, so the loop
+// indexes no argument array by lane; the state is accessed without
+// non-temporal hints, and factor tables are a separate instance (TAB):
+// branches around the loads and stores make the compiler wait for every
+// access, the prefetch included.  Complex64 runs on the fp32 matrix cores
+// (v_mfma_f32_16x16x4f32, operands and sums in fp32, the precision of its
+// amplitudes; the vector kernels widen them to fp64), whose 16x16x4 step
+// takes half the cycles of the fp64 one, so a five-qubit group's 4096
+// multiply-adds per coset fit under the memory time of its 8-byte
+// amplitudes.  Complex128 runs on v_mfma_f64_16x16x4f64.  Accumulator
+// register j of lane l holds row 4 (l / 16) + j of its tile for fp32 and
+// row 4 j + l / 16 for fp64 (both measured).
+typedef float MfmaAcc32 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MfmaStep;
+template <>
+struct MfmaStep<float> {
+  using Acc = MfmaAcc32;
+  static constexpr bool kRowsByGroup = true;  // register j: row 4 (l / 16) + j
+  static __device__ __forceinline__ Acc step(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfmaStep<double> {
+  using Acc = MfmaAcc;
+  static constexpr bool kRowsByGroup = false;  // register j: row 4 j + l / 16
+  static __device__ __forceinline__ Acc step(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// The multiply-and-store of one tile whose inputs x (NX complex values of
+// lane l's coset, local indices 4 s + l / 16) are in registers; dst is the
+// tile's first element plus the lane's column and its output offset.
+template <typename R, int K, bool TAB>
+__device__ __forceinline__ void mfmap_tile(const MfmaArgs& a, typename Vec<R>::V* v, const R* sm, int mo,
+                                           const typename Vec<R>::V (&x)[1 << (K - 2)], typename Vec<R>::V* dst) {
+  using M = MfmaStep<R>;
+  using V = typename Vec<R>::V;
+  constexpr int D = 1 << K;
+  constexpr int RT = 2 * D / 16;  // row tiles
+  constexpr int S = 2 * D / 4;    // slices of depth 4
+  constexpr int NX = D / 4;
+  typename M::Acc acc[RT];
+#pragma unroll
+  for (int i = 0; i < RT; i++) acc[i] = typename M::Acc{0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    const R b = s < NX ? x[s].x : x[s - NX].y;
+#pragma unroll
+    for (int i = 0; i < RT; i++) acc[i] = M::step(sm[(i * S + s) * 64 + mo], b, acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < RT / 2; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      R yr = acc[i][j], yi = acc[i + RT / 2][j];
+      V* const o = dst + a.off[M::kRowsByGroup ? 16 * i + j : 16 * i + 4 * j];
+      if constexpr (TAB) {
+        double dr = yr, di = yi;
+        apply_tables(a.tabs, a.nt, uint64_t(o - v), dr, di);
+        yr = R(dr);
+        yi = R(di);
+      }
+      *o = V{yr, yi};
+    }
+}
+
+template <typename R, int K, bool TAB>
+__global__ __launch_bounds__(kMfmaBlock) void kron_mfmap_kernel(MfmaArgs a, typename Vec<R>::V* __restrict__ v) {
+  using V = typename Vec<R>::V;
+  constexpr int D = 1 << K;
+  constexpr int RT = 2 * D / 16;
+  constexpr int S = 2 * D / 4;
+  constexpr int NX = D / 4;
+  __shared__ R sm[RT * S * 64];
+  const R* lm = reinterpret_cast<const R*>(a.lmat);
+  for (int e = threadIdx.x; e < RT * S * 64; e += kMfmaBlock) sm[e] = lm[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  // off[] is additive over disjoint index bits: the lane's inputs are
+  // local indices 4 s + kq, its outputs 16 i + 4 kq + j (fp32) or
+  // 16 i + 4 j + kq (fp64)
+  const int64_t in_lo = ((kq & 1) ? a.off[1] : 0) + ((kq & 2) ? a.off[2] : 0);
+  const int64_t out_lane =
+      MfmaStep<R>::kRowsByGroup ? ((kq & 1) ? a.off[4] : 0) + ((kq & 2) ? a.off[8] : 0) : in_lo;
+  const int64_t waves = int64_t(gridDim.x) * (kMfmaBlock / 64);
+  // a tile is 16 consecutive cosets; every group qubit is >= 4, so the
+  // coset bits 0-3 (the lane's column) pass through unchanged and the
+  // tile's first element is wave-uniform
+  auto tile_first = [&](int64_t t) {
+    int64_t b = t * 16;
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      const int p = a.sorted[j];
+      b = (b & ((int64_t(1) << p) - 1)) | ((b >> p) << (p + 1));
+    }
+    return b;
+  };
+  auto load = [&](V (&x)[NX], int64_t t) {
+    const V* src = v + tile_first(t) + col + in_lo;
+#pragma unroll
+    for (int s = 0; s < NX; s++) x[s] = src[a.off[4 * s]];
+  };
+  int64_t t = int64_t(blockIdx.x) * (kMfmaBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (t >= a.ntiles) return;
+  int mo = lane;
+  // two input buffers in turn: while one tile is multiplied, the next
+  // tile's loads are in flight into the other (the last tile's inputs are
+  // loaded again past the end: in bounds, unused; tiles are disjoint, so a
+  // tile's outputs are never among the inputs in flight)
+  V xa[NX], xb[NX];
+  load(xa, t);
+  for (;;) {
+    load(xb, std::min(t + waves, a.ntiles - 1));
+    asm volatile("" : "+v"(mo));  // re-read the matrix for every tile (no hoisting)
+    mfmap_tile<R, K, TAB>(a, v, sm, mo, xa, v + tile_first(t) + col + out_lane);
+    t += waves;
+    if (t >= a.ntiles) break;
+    load(xa, std::min(t + waves, a.ntiles - 1));
+    asm volatile("" : "+v"(mo));
+    mfmap_tile<R, K, TAB>(a, v, sm, mo, xb, v + tile_first(t) + col + out_lane);
+    t += waves;
+    if (t >= a.ntiles) break;
+  }
+}
+
+// resident blocks per CU of an instance, from its registers and LDS
+template <typename R, int K, bool TAB>
+int mfmap_resident() {
+  static const int nb = [] {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kron_mfmap_kernel<R, K, TAB>, kMfmaBlock, 0) != hipSuccess)
+      b = 0;
+    return std::max(b, 1);
+  }();
+  return nb;
+}
+
+template <typename R, int K, bool TAB>
+void launch_mfmap_k(const MfmaArgs& a, int num_cus, hipStream_t stream, void* state) {
+  // persistent: as many blocks as stay resident together, so that no block
+  // waits for another block's whole share of the tiles
+  const int64_t want = (a.ntiles + 3) / 4;
+  const int64_t resident = int64_t(num_cus) * mfmap_resident<R, K, TAB>();
+  const dim3 grid(unsigned(std::max<int64_t>(1, std::min(want, resident)))), block(kMfmaBlock);
+  hipLaunchKernelGGL((kron_mfmap_kernel<R, K, TAB>), grid, block, 0, stream, a,
+                     static_cast<typename Vec<R>::V*>(state));
+}
+
+template <typename R>
+void launch_mfmap(const MfmaArgs& a, int k, int num_cus, hipStream_t stream, void* state) {
+  if (k == 4) {
+    if (a.nt) launch_mfmap_k<R, 4, true>(a, num_cus, stream, state);
+    else launch_mfmap_k<R, 4, false>(a, num_cus, stream, state);
+  } else {
+    if (a.nt) launch_mfmap_k<R, 5, true>(a, num_cus, stream, state);
+    else launch_mfmap_k<R, 5, false>(a, num_cus, stream, state);
+  }
 }
 
 // Staging layout for the group S (ascending) on n qubits; false if the
@@ -819,11 +990,19 @@ diaq_status_t plan_big_greedy(const diaq_gate_t* gates, int64_t ngates, int n, i
 // of at most four qubits costs its memory pass; a dense five-qubit group's
 // 4096 FMAs per coset take longer than that pass (n = 28: 1.85 against
 // 1.44 ms in complex128; in complex64, whose narrower groups run about
-// 0.8 ms per pass, 1.45 ms).
-double plan_cost(const std::vector<BigOp>& ops, diaq_dtype_t dt) {
+// 0.8 ms per pass, 1.45 ms on the vector kernels), less on the pipelined
+// matrix cores, which take the groups whose qubits are all >= 4.
+double plan_cost(const std::vector<BigOp>& ops, diaq_dtype_t dt, int n) {
   const double five = dt == DIAQ_C128 ? 1.3 : 1.8;
   double c = 0;
-  for (const BigOp& op : ops) c += (!op.raw && op.k == 5) ? five : 1.0;
+  // on the pipelined matrix cores (groups whose qubits are all >= 4):
+  // complex64 one pass (n = 28: 0.87 ms, as a four-qubit group),
+  // complex128 1.2 (1.74 ms)
+  const double five_mfma = dt == DIAQ_C128 ? 1.2 : 1.0;
+  for (const BigOp& op : ops) {
+    if (op.raw || op.k != 5) c += 1.0;
+    else c += mfma_group(op.q, op.k, n) ? five_mfma : five;
+  }
   return c;
 }
 
@@ -838,11 +1017,11 @@ diaq_status_t plan_big(const diaq_gate_t* gates, int64_t ngates, int n, int kmax
   // keep the plan of least modelled time (QFT-29: 24 operations with five
   // qubits against 25 with three, 97 against 81 ms)
   if (kmax == 5) {
-    double best = plan_cost(*ops, dt);
+    double best = plan_cost(*ops, dt, n);
     for (int k : {4, 3}) {
       std::vector<BigOp> alt;
       DIAQ_TRY(plan_big_greedy(gates, ngates, n, k, &alt));
-      const double c = plan_cost(alt, dt);
+      const double c = plan_cost(alt, dt, n);
       if (c < best) {
         best = c;
         ops->swap(alt);
@@ -860,7 +1039,17 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
   OpTables tabs;
   const bool use_mfma = ctx->tuning.kron_split == 4 || ctx->tuning.kron_split == 5;
   const bool g3 = ctx->tuning.kron_split == 6;
-  std::vector<size_t> loff3(ops.size(), SIZE_MAX);
+  // pipelined matrix-core groups (all qubits >= 4): knob 7, and by default
+  // complex64 groups of four and five qubits and complex128 groups of five
+  // (n = 28, mean over positions: complex64 five qubits 1465 -> 869 us,
+  // four 921 -> 891 us; complex128 five 1969 -> 1738 us, while its four-
+  // qubit groups stay faster on the split kernel, 6.1 against 4.9 TB/s)
+  auto use_mfmap = [&](const BigOp& op) {
+    if (op.raw || !mfma_group(op.q, op.k, n)) return false;
+    const int ks = ctx->tuning.kron_split;
+    return ks == 7 || (ks == 0 && (dt == DIAQ_C64 || op.k == 5));
+  };
+  std::vector<size_t> loff3(ops.size(), SIZE_MAX), loffp(ops.size(), SIZE_MAX);
   for (size_t k = 0; k < ops.size(); k++) {
     moff[k] = mats.size();
     for (const Cd& z : ops[k].m) {
@@ -882,6 +1071,21 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
       loff[k] = mats.size();
       const std::vector<double> lm = mfma_operands(ops[k].m, ops[k].k);
       mats.insert(mats.end(), lm.begin(), lm.end());
+    }
+    if (use_mfmap(ops[k])) {
+      // the operands in the state's precision (complex64: fp32, two per
+      // double slot), 16-byte aligned
+      if (mats.size() & 1) mats.push_back(0.0);
+      loffp[k] = mats.size();
+      const std::vector<double> lm = mfma_operands(ops[k].m, ops[k].k);
+      if (dt == DIAQ_C128) {
+        mats.insert(mats.end(), lm.begin(), lm.end());
+      } else {
+        std::vector<float> lf(lm.begin(), lm.end());
+        const size_t at = mats.size();
+        mats.resize(at + (lf.size() + 1) / 2, 0.0);
+        std::memcpy(mats.data() + at, lf.data(), lf.size() * sizeof(float));
+      }
     }
     // headers with the index bits of the operation's 2^k row offsets, for
     // kernels that decode each table once per coset
@@ -914,11 +1118,31 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
     // block by default (n = 28, mean over positions: four qubits with 4 rows
     // per wave 5.46 -> 6.00 TB/s, five qubits with 8 rows 4.54 -> 4.70);
     // complex64 keeps one lane per coset (its fp64 arithmetic, not memory,
-    // is the limit: split 4.21 against 4.76 TB/s for four qubits)
+    // is the limit: split 4.21 against 4.76 TB/s for four qubits) where the
+    // pipelined fp32 matrix-core kernel does not apply (a qubit below 4)
     int split = ctx->tuning.kron_split;
-    if (split == 0) split = dt == DIAQ_C128 ? (op.k == 4 ? 3 : 2) : 1;
+    if (split == 0 || split == 7) split = dt == DIAQ_C128 ? (op.k == 4 ? 3 : 2) : 1;
     if (op.raw) {
       DIAQ_TRY(launch_kron_apply(ctx, ctx->stream, op.lg, n, dt, state, false, tk, nt));
+    } else if (loffp[k] != SIZE_MAX) {
+      // dense 4-5 qubit groups on the matrix cores, pipelined
+      MfmaArgs ma;
+      std::memset(&ma, 0, sizeof(ma));
+      ma.ntiles = (N >> op.k) / 16;
+      ma.nt = nt;
+      ma.nt_io = ntp;
+      for (int j = 0; j < op.k; j++) ma.sorted[j] = op.q[j];
+      for (int r = 0; r < (1 << op.k); r++) {
+        int64_t o = 0;
+        for (int j = 0; j < op.k; j++)
+          if ((r >> j) & 1) o |= int64_t(1) << op.q[j];
+        ma.off[r] = o;
+      }
+      ma.lmat = dm + loffp[k];
+      ma.tabs = tk;
+      if (dt == DIAQ_C128) launch_mfmap<double>(ma, op.k, ctx->num_cus, ctx->stream, state);
+      else launch_mfmap<float>(ma, op.k, ctx->num_cus, ctx->stream, state);
+      DIAQ_HIP(hipGetLastError());
     } else if (loff[k] != SIZE_MAX) {
       // dense 4-5 qubit groups on the matrix cores
       MfmaArgs ma;

@@ -1,7 +1,8 @@
 """Every selectable shape of the Alg. 3 kernels, forced through the tuning
 knobs: dense 4- and 5-qubit groups one lane per coset, with their rows
 split over the waves of a block (8 or 4 rows per wave), or as fp64
-matrix-core products (matrix re-read from LDS or held in registers); the LDS staging
+matrix-core products (matrix re-read from LDS or held in registers), or
+as pipelined matrix-core products (fp32 for complex64); the LDS staging
 threshold for groups of up to four qubits (never, default, up to qubit 5);
 non-temporal state streams of the per-coset kernels on and off.  Each
 variant runs workloads whose groups sit on the lowest qubits, in the
@@ -34,6 +35,7 @@ _KNOBS = {
     "mfma": {"kron_split": 4},
     "mfma_hold": {"kron_split": 5},
     "split8_gauss": {"kron_split": 6},
+    "mfma_pipe": {"kron_split": 7},
     "order_xcd": {"kron_order": 1, "kron_stage_qubit": -1},
     "order_halves": {"kron_order": 2, "kron_stage_qubit": -1},
     "order_scatter": {"kron_order": 3},
@@ -96,6 +98,6 @@ def test_kron_variants_match_oracle(cases, ctx, knobs):
 
 
 def test_kron_knobs_rejected_out_of_range(ctx):
-    for bad in ({"kron_split": 7}, {"kron_stage_qubit": 7}, {"kron_nontemporal": 2}, {"kron_order": 4}):
+    for bad in ({"kron_split": 8}, {"kron_stage_qubit": 7}, {"kron_nontemporal": 2}, {"kron_order": 4}):
         with pytest.raises(D.DiaqError):
             D.set_tuning(ctx, **bad)
