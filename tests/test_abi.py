@@ -165,6 +165,16 @@ def test_plan_count_host_only(lib):
     for (kron, k), c in counts.items():
         assert D.plan_count(gates, n, D.make_plan(kron=kron, fuse=True, max_fused_qubits=k))[0] == c, (kron, k)
     assert D.plan_count(W.qft(24), 24, D.make_plan(kron=True, fuse=True, max_fused_qubits=3))[0] == 20
+    # the five-qubit cost model: groups whose qubits are all >= 4 (n >= 9)
+    # run on the matrix cores, one pass in complex64, so both precisions
+    # keep the five-qubit grouping at n = 28; at n = 8 no group qualifies
+    # and complex64 (1.8 passes per five-qubit group) keeps the four-qubit
+    # grouping while complex128 (1.3) does not
+    five = D.make_plan(kron=True, fuse=True, max_fused_qubits=5)
+    assert D.plan_count(gates, n, five, dtype=torch.complex64)[0] == 78
+    small = W.random_layered(8, 20, 28)
+    assert D.plan_count(small, 8, five, dtype=torch.complex64)[0] == 22
+    assert D.plan_count(small, 8, five, dtype=torch.complex128)[0] == 17
     for kw in (dict(fuse=True, max_fused_qubits=4), dict(kron=True, fuse=True, max_fused_qubits=6),
                dict(fuse=True, max_fused_qubits=-1)):
         with pytest.raises(D.DiaqError) as ei:
