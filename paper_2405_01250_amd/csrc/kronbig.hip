@@ -595,6 +595,22 @@ std::vector<double> mfma_operands(const std::vector<Cd>& m, int k) {
   return out;
 }
 
+// The operands of kron_mfmap_kernel's three products in operand order: entry
+// ((p RT + i) S + s) 64 + l holds row 16 i + l % 16, column 4 s + l / 16 of
+// Re M (p = 0), Im M (p = 1) or Re M + Im M (p = 2); RT = D / 16, S = D / 4.
+std::vector<double> mfmap_operands(const std::vector<Cd>& m, int k) {
+  const int D = 1 << k, RT = D / 16, S = D / 4;
+  std::vector<double> out(size_t(3) * RT * S * 64);
+  for (int p = 0; p < 3; p++)
+    for (int i = 0; i < RT; i++)
+      for (int s = 0; s < S; s++)
+        for (int l = 0; l < 64; l++) {
+          const Cd z = m[size_t(16 * i + l % 16) * D + (4 * s + l / 16)];
+          out[((size_t(p) * RT + i) * S + s) * 64 + l] = p == 0 ? z.real() : p == 1 ? z.imag() : z.real() + z.imag();
+        }
+  return out;
+}
+
 // The matrix-core kernel needs 16 cosets of consecutive elements per tile
 // (every group qubit >= 4) and at least one tile.
 inline bool mfma_group(const int* q, int k, int n) { return (k == 4 || k == 5) && q[0] >= 4 && n >= k + 4; }
@@ -655,30 +671,37 @@ struct MfmaStep<double> {
 
 // The multiply-and-store of one tile whose inputs x (NX complex values of
 // lane l's coset, local indices 4 s + l / 16) are in registers; dst is the
-// tile's first element plus the lane's column and its output offset.
+// tile's first element plus the lane's column and its output offset.  The
+// complex product M v = (A + iB)(x + iy) takes three real D x D products
+// instead of the four of the real 2D x 2D form: p1 = A x, p2 = B y,
+// p3 = (A + B)(x + y), then Re = p1 - p2 and Im = p3 - p1 - p2 (48 instead
+// of 64 matrix-core steps per five-qubit tile).
 template <typename R, int K, bool TAB>
 __device__ __forceinline__ void mfmap_tile(const MfmaArgs& a, typename Vec<R>::V* v, const R* sm, int mo,
                                            const typename Vec<R>::V (&x)[1 << (K - 2)], typename Vec<R>::V* dst) {
   using M = MfmaStep<R>;
   using V = typename Vec<R>::V;
   constexpr int D = 1 << K;
-  constexpr int RT = 2 * D / 16;  // row tiles
-  constexpr int S = 2 * D / 4;    // slices of depth 4
-  constexpr int NX = D / 4;
-  typename M::Acc acc[RT];
+  constexpr int RT = D / 16;  // row tiles of each D x D product
+  constexpr int S = D / 4;    // slices of depth 4
+  typename M::Acc p1[RT], p2[RT], p3[RT];
 #pragma unroll
-  for (int i = 0; i < RT; i++) acc[i] = typename M::Acc{0, 0, 0, 0};
+  for (int i = 0; i < RT; i++) p1[i] = p2[i] = p3[i] = typename M::Acc{0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < S; s++) {
-    const R b = s < NX ? x[s].x : x[s - NX].y;
+    const R bx = x[s].x, by = x[s].y, bs = bx + by;
 #pragma unroll
-    for (int i = 0; i < RT; i++) acc[i] = M::step(sm[(i * S + s) * 64 + mo], b, acc[i]);
+    for (int i = 0; i < RT; i++) {
+      p1[i] = M::step(sm[((0 * RT + i) * S + s) * 64 + mo], bx, p1[i]);
+      p2[i] = M::step(sm[((1 * RT + i) * S + s) * 64 + mo], by, p2[i]);
+      p3[i] = M::step(sm[((2 * RT + i) * S + s) * 64 + mo], bs, p3[i]);
+    }
   }
 #pragma unroll
-  for (int i = 0; i < RT / 2; i++)
+  for (int i = 0; i < RT; i++)
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-      R yr = acc[i][j], yi = acc[i + RT / 2][j];
+      R yr = p1[i][j] - p2[i][j], yi = p3[i][j] - p1[i][j] - p2[i][j];
       V* const o = dst + a.off[M::kRowsByGroup ? 16 * i + j : 16 * i + 4 * j];
       if constexpr (TAB) {
         double dr = yr, di = yi;
@@ -694,12 +717,11 @@ template <typename R, int K, bool TAB>
 __global__ __launch_bounds__(kMfmaBlock) void kron_mfmap_kernel(MfmaArgs a, typename Vec<R>::V* __restrict__ v) {
   using V = typename Vec<R>::V;
   constexpr int D = 1 << K;
-  constexpr int RT = 2 * D / 16;
-  constexpr int S = 2 * D / 4;
   constexpr int NX = D / 4;
-  __shared__ R sm[RT * S * 64];
+  constexpr int TABN = 3 * (D / 16) * (D / 4) * 64;  // the three operand tables
+  __shared__ R sm[TABN];
   const R* lm = reinterpret_cast<const R*>(a.lmat);
-  for (int e = threadIdx.x; e < RT * S * 64; e += kMfmaBlock) sm[e] = lm[e];
+  for (int e = threadIdx.x; e < TABN; e += kMfmaBlock) sm[e] = lm[e];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
@@ -1077,7 +1099,7 @@ diaq_status_t run_big(diaq_ctx* ctx, const std::vector<BigOp>& ops, int n, diaq_
       // double slot), 16-byte aligned
       if (mats.size() & 1) mats.push_back(0.0);
       loffp[k] = mats.size();
-      const std::vector<double> lm = mfma_operands(ops[k].m, ops[k].k);
+      const std::vector<double> lm = mfmap_operands(ops[k].m, ops[k].k);
       if (dt == DIAQ_C128) {
         mats.insert(mats.end(), lm.begin(), lm.end());
       } else {
