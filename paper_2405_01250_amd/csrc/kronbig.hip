@@ -629,25 +629,26 @@ void launch_mfma(const MfmaArgs& a, int k, bool hold, int num_cus, hipStream_t s
   else hipLaunchKernelGGL((kron_mfma_kernel<R, 5, false>), grid, block, 0, stream, a, v);
 }
 
-// Pipelined matrix-core groups: the same real (2D x 2D) * (2D x 16)
-// product per 16 cosets as kron_mfma_kernel, arranged so that the memory
-// stream and the matrix cores overlap.  Each wave loads the inputs of its
-// next tile into a second register buffer before it multiplies the current
-// one; the matrix stays in LDS (a.lmat holds the operand-order table in the
-// state's precision), re-read for every tile, which leaves registers for
-// four or more waves per SIMD; lane l's element offsets split into a
-// wave-uniform part and a part fixed by l / 16, formed once, so the loop
-// indexes no argument array by lane; the state is accessed without
-// non-temporal hints, and factor tables are a separate instance (TAB):
-// branches around the loads and stores make the compiler wait for every
-// access, the prefetch included.  Complex64 runs on the fp32 matrix cores
-// (v_mfma_f32_16x16x4f32, operands and sums in fp32, the precision of its
-// amplitudes; the vector kernels widen them to fp64), whose 16x16x4 step
-// takes half the cycles of the fp64 one, so a five-qubit group's 4096
-// multiply-adds per coset fit under the memory time of its 8-byte
-// amplitudes.  Complex128 runs on v_mfma_f64_16x16x4f64.  Accumulator
-// register j of lane l holds row 4 (l / 16) + j of its tile for fp32 and
-// row 4 j + l / 16 for fp64 (both measured).
+// Pipelined matrix-core groups: the group's D x D complex matrix applied to
+// 16 cosets at a time on the matrix cores (a tile: lane l holds column
+// l % 16, one coset, at depth l / 16 of every operand, as in
+// kron_mfma_kernel), arranged so that the memory stream and the matrix
+// cores overlap.  Each wave loads the inputs of its next tile into a
+// second register buffer before it multiplies the current one; the
+// operand tables stay in LDS (a.lmat holds them in the state's precision),
+// re-read for every tile, which leaves registers for three or more waves
+// per SIMD; lane l's element offsets split into a wave-uniform part and a
+// part fixed by l / 16, formed once, so the loop indexes no argument array
+// by lane; the state is accessed without non-temporal hints, and factor
+// tables are a separate instance (TAB): branches around the loads and
+// stores make the compiler wait for every access, the prefetch included.
+// Complex64 runs on the fp32 matrix cores (v_mfma_f32_16x16x4f32, operands
+// and sums in fp32, the precision of its amplitudes; the vector kernels
+// widen them to fp64), whose 16x16x4 step takes half the cycles of the
+// fp64 one, so a five-qubit group's products fit under the memory time of
+// its 8-byte amplitudes.  Complex128 runs on v_mfma_f64_16x16x4f64.
+// Accumulator register j of lane l holds row 4 (l / 16) + j of its tile
+// for fp32 and row 4 j + l / 16 for fp64 (both measured).
 typedef float MfmaAcc32 __attribute__((ext_vector_type(4)));
 
 template <typename R>
