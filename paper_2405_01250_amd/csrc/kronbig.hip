@@ -778,8 +778,10 @@ template <typename R, int K, bool TAB>
 int mfmap_resident() {
   static const int nb = [] {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kron_mfmap_kernel<R, K, TAB>, kMfmaBlock, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kron_mfmap_kernel<R, K, TAB>, kMfmaBlock, 0) != hipSuccess) {
+      (void)hipGetLastError();  // one block per CU, and no error left for the launch check
       b = 0;
+    }
     return std::max(b, 1);
   }();
   return nb;
